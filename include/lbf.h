@@ -1,0 +1,195 @@
+/*
+ * lbf.h -- C ABI of the MI355X (gfx950) fluctuating lattice Boltzmann
+ * library: the D3Q19 collide-and-stream update with thermal noise of
+ * Duenweg, Schiller & Ladd, "Statistical mechanics of the fluctuating lattice
+ * Boltzmann equation" (arXiv:0707.1581).
+ *
+ * What one step computes (per lattice site r, step count t):
+ *   1. modes m_k = sum_i e_ki n_i(r) of the 19 populations with the Table II
+ *      basis (Sec. III, Eq. modes with the unscaled basis);
+ *   2. rho = m_0, j = (m_1, m_2, m_3) (Eqs. defrho, defj) and the
+ *      equilibrium stress modes of Eq. derived_equil_distrib (k = 4..9;
+ *      the kinetic modes k = 10..18 have no equilibrium part);
+ *   3. for every non-conserved mode k = 4..18
+ *        m*_k = m_k^eq + gamma_k (m_k - m_k^eq) + sqrt(mu rho w_k (1 - gamma_k^2)) r_k
+ *      (Eqs. updaterule and FDT, Sec. IV), with mu = kT / c_s^2 = 3 kT in
+ *      lattice units (Sec. VI), w_k the Table II normalisers, rho the local
+ *      density and r_k unit Gaussians; conserved modes k <= 3 are unchanged;
+ *   4. back-transform n*_i = a_i sum_k e_ki m*_k / w_k and push along the
+ *      links, n_i(r + c_i, t + 1) = n*_i(r, t), on a periodic box (Eq. LBE).
+ * Mode rates: gamma_4 = gamma_bulk, gamma_5..9 = gamma_shear,
+ * gamma_10..15 = gamma_odd (third-order kinetic modes), gamma_16..18 =
+ * gamma_even (fourth-order kinetic modes).
+ *
+ * Velocity order i: 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 = (+1,+1,0)
+ * (-1,-1,0) (+1,-1,0) (-1,+1,0) (+1,0,+1) (-1,0,-1) (+1,0,-1) (-1,0,+1)
+ * (0,+1,+1) (0,-1,-1) (0,+1,-1) (0,-1,+1); weights a_i = 1/3, 1/18, 1/36
+ * (Sec. II).
+ *
+ * Random numbers: Philox4x32-10 keyed on the seed with counter
+ * (site, t mod 2^32, call, t >> 32), 24-bit uniforms cut from each three
+ * consecutive output words (most significant first), Box-Muller on
+ * consecutive uniform pairs (cos first), normal s -> mode 4 + s.  The site
+ * is the linear index x + nx (y + ny z) within the lattice, so a replica of
+ * a batch draws exactly the numbers of the same lattice run alone.
+ *
+ * State: one caller-owned device buffer holding, for every population i and
+ * site, the scaled deviation delta_i = (n_i - a_i rho0) / (a_i rho0) in the
+ * storage type (fp32, fp16 or bf16), as 19 planes [i][z][y][x] (x fastest),
+ * updated in place with the AA access pattern: at even t, n_i(r) is held in
+ * plane i at site r; at odd t, n_i(r) is held in plane opp(i) at site
+ * r - c_i (opp(i) is the index of -c_i).  Callers never need this: all
+ * gathers return parity-resolved populations, moments and modes.
+ *
+ * Conventions of every call:
+ *   - device pointers (d_*) are caller-owned, contiguous, 256-byte aligned
+ *     device memory; the library never frees them;
+ *   - the stream is the caller's hipStream_t passed as void*; every kernel
+ *     of a context runs on it; only lb_check and lb_autotune synchronise;
+ *   - argument errors are detected before anything is enqueued (nothing is
+ *     done); launch failures return LB_EDEVICE; lb_last_error() gives the
+ *     message of the last failure on the calling thread;
+ *   - a context is not thread-safe; separate contexts are independent.
+ */
+#ifndef LBF_H
+#define LBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum lb_status {
+  LB_OK = 0,
+  LB_EINVAL = -1,       /* invalid argument; nothing enqueued            */
+  LB_EDEVICE = -2,      /* HIP runtime or launch failure                 */
+  LB_ESTATE = -3,       /* lb_check found NaN or rho <= 0 sites          */
+  LB_EUNSUPPORTED = -4  /* valid request this build does not provide     */
+};
+
+enum lb_storage { LB_F32 = 0, LB_F16 = 1, LB_BF16 = 2 };
+
+enum lb_init_kind {
+  LB_INIT_REST = 0,    /* n_i = a_i rho0                                          */
+  LB_INIT_THERMAL = 1, /* every normalised mode an independent unit Gaussian:     */
+                       /* n_i = a_i rho0 + sqrt(mu rho0 a_i) sum_k ehat_ki z_k    */
+                       /* (Eqs. xdef, x_s); normals from Philox stream 1          */
+  LB_INIT_FIELDS = 2,  /* n_i = n_i^eq(rho, u) by Eq. derived_equil_distrib from  */
+                       /* d_fields (4, nz, ny, nx) fp32 = rho, ux, uy, uz         */
+  LB_INIT_KEEP = 3     /* keep the buffer's contents as the state at step t0      */
+};
+
+enum lb_thermal_modes {
+  LB_THERMAL_ALL = 0,        /* noise on every non-conserved mode (the paper's    */
+                             /* detailed-balance collision, Sec. IV)              */
+  LB_THERMAL_STRESS_ONLY = 1 /* noise on the six stress modes only: the earlier   */
+                             /* model the paper contrasts (kinetic modes get no   */
+                             /* noise, violating detailed balance, Sec. IV)       */
+};
+
+typedef struct {
+  int32_t nx, ny, nz;     /* periodic box, each >= 1 (1 makes that axis trivial)  */
+  int32_t storage;        /* enum lb_storage                                      */
+  double rho0;            /* > 0: reference density and deviation base            */
+  double kT;              /* >= 0: mu = 3 kT; kT = 0 gives the deterministic update */
+  double gamma_bulk;      /* each gamma in [-1, 1] (linear stability, Sec. IV)    */
+  double gamma_shear;
+  double gamma_odd;
+  double gamma_even;
+  uint64_t seed;          /* Philox key                                           */
+  int32_t thermal_modes;  /* enum lb_thermal_modes                                */
+  int32_t reserved;       /* must be 0                                            */
+} lb_params;
+
+typedef struct lb_ctx lb_ctx; /* opaque, library-owned */
+
+/* Bytes of the state buffer: 19 * nx * ny * nz * sizeof(storage); 0 if the
+ * parameters are invalid. */
+size_t lb_state_bytes(const lb_params* p);
+
+/* Validate p and create a context that updates d_state on hip_stream.
+ * Enqueues the initial state (init_kind) as the state at step count t0
+ * (t0 >= 0); d_fields is required for LB_INIT_FIELDS and ignored otherwise.
+ * The context stores p by value. */
+int lb_init(const lb_params* p, void* d_state, void* hip_stream, int32_t init_kind,
+            const float* d_fields, int64_t t0, lb_ctx** out);
+
+/* Enqueue nsteps >= 0 steps (collide with noise keyed on the current t,
+ * then push).  Full chunks of steps are replayed from a HIP graph. */
+int lb_step(lb_ctx* ctx, int64_t nsteps);
+
+/* Parity-resolved gathers into caller-owned fp32 device buffers, each laid
+ * out (count, nz, ny, nx):
+ *   lb_populations: 19 planes, n_i;
+ *   lb_moments:      4 planes, rho, jx, jy, jz (Eqs. defrho, defj);
+ *   lb_modes:       19 planes, m_k = sum_i e_ki (n_i - a_i rho0), so m_0 =
+ *                   rho - rho0 and m_1..3 = j. */
+int lb_populations(lb_ctx* ctx, float* d_out);
+int lb_moments(lb_ctx* ctx, float* d_out);
+int lb_modes(lb_ctx* ctx, float* d_out);
+
+/* Synchronising health check: counts sites with a non-finite population or
+ * rho <= 0 into *n_bad and writes the lattice sums (sum rho, sum jx, sum jy,
+ * sum jz) in fp64 to sums_out[4] (either pointer may be NULL).  Returns
+ * LB_ESTATE when *n_bad > 0. */
+int lb_check(lb_ctx* ctx, int64_t* n_bad, double* sums_out);
+
+/* Completed steps t (the state held is the post-stream state at t). */
+int64_t lb_step_count(const lb_ctx* ctx);
+
+/* Release a context (a batch, a single lattice or a view). */
+void lb_destroy(lb_ctx* ctx);
+
+const char* lb_strerror(int code);
+const char* lb_last_error(void);
+
+/* ---- ensembles: many independent lattices in one launch per step ---- */
+
+/* Bytes of the pool for nrep replicas: each replica's state rounded up to
+ * 256 bytes, in order; 0 if any replica is invalid. */
+size_t lb_batch_pool_bytes(const lb_params* reps, int32_t nrep);
+
+/* Byte offset of replica r in the pool. */
+size_t lb_batch_offset(const lb_params* reps, int32_t nrep, int32_t r);
+
+/* Create an ensemble of nrep >= 1 replicas with their own box, rates,
+ * temperature and seed (one storage type for all), laid out in d_pool as by
+ * lb_batch_pool_bytes.  init_kind: LB_INIT_REST, LB_INIT_THERMAL or
+ * LB_INIT_KEEP (LB_INIT_FIELDS returns LB_EUNSUPPORTED). */
+int lb_batch_init(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_stream,
+                  int32_t init_kind, int64_t t0, lb_ctx** out);
+
+/* Advance every replica by nsteps; one kernel launch per step covers all
+ * replicas, and full chunks of steps are replayed from a HIP graph. */
+int lb_batch_step(lb_ctx* batch, int64_t nsteps);
+
+/* A non-owning context for replica r (gathers and lb_check only; its step
+ * count is the batch's).  Release with lb_destroy before the batch. */
+int lb_batch_view(lb_ctx* batch, int32_t replica, lb_ctx** view);
+
+/* ---- launch schedule and autotuning ---- */
+
+typedef struct {
+  int32_t block;      /* threads per workgroup: 64, 128, 256 or 512          */
+  int32_t order;      /* tile order: 0 replica order, 1 largest replica      */
+                      /* first, 2 round-robin interleave of replicas         */
+  int32_t xcd_remap;  /* 1: give each XCD a contiguous range of tiles        */
+  int32_t graph_chunk;/* steps per graph replay (>= 2, even)                 */
+} lb_schedule;
+
+int lb_get_schedule(const lb_ctx* ctx, lb_schedule* out);
+int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
+
+/* Time every candidate schedule on a scratch copy of the state (the state
+ * and step count of ctx are unchanged), apply the fastest, and write a JSON
+ * report (one object per candidate with its mean step time) into report
+ * (NUL-terminated, truncated to report_len).  steps >= 2 per candidate. */
+int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBF_H */

@@ -1,0 +1,700 @@
+// lbf.hip -- host side of the C ABI declared in include/lbf.h: argument
+// validation, per-lattice coefficient tables, contexts, kernel dispatch,
+// HIP-graph replay of step chunks, ensembles and the schedule autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "lbf.h"
+#include "lbf_kernels.h"
+
+using namespace lbf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(LB_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+size_t elem_size(int storage) { return storage == LB_F32 ? 4 : 2; }
+
+int validate(const lb_params* p) {
+  if (!p) return fail(LB_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LB_EINVAL, "box dimensions must be >= 1");
+  if (p->storage < LB_F32 || p->storage > LB_BF16) return fail(LB_EINVAL, "unknown storage type");
+  if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LB_EINVAL, "rho0 must be finite and > 0");
+  if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return fail(LB_EINVAL, "kT must be finite and >= 0");
+  const double g[4] = {p->gamma_bulk, p->gamma_shear, p->gamma_odd, p->gamma_even};
+  for (double v : g)
+    if (!(v >= -1.0 && v <= 1.0)) return fail(LB_EINVAL, "every gamma must lie in [-1, 1]");
+  if (p->thermal_modes != LB_THERMAL_ALL && p->thermal_modes != LB_THERMAL_STRESS_ONLY)
+    return fail(LB_EINVAL, "unknown thermal_modes");
+  if (p->reserved != 0) return fail(LB_EINVAL, "reserved must be 0");
+  const uint64_t n = (uint64_t)p->nx * (uint64_t)p->ny * (uint64_t)p->nz;
+  if (n >= (1ull << 32)) return fail(LB_EUNSUPPORTED, "lattices of 2^32 sites or more are not supported");
+  return LB_OK;
+}
+
+uint64_t sites_of(const lb_params& p) { return (uint64_t)p.nx * (uint64_t)p.ny * (uint64_t)p.nz; }
+
+// Division by an invariant integer d (Granlund & Montgomery 1994):
+// q = (t + ((n - t) >> s1)) >> s2 with t = mulhi(n, m).
+void div_magic(uint32_t d, uint32_t& m, uint32_t& s1, uint32_t& s2) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  s1 = l > 0 ? 1 : 0;
+  s2 = l > 0 ? l - 1 : 0;
+}
+
+// Table II normalisers w_k (36 w_k in W36).
+double wk(int k) { return (double)W36[k] / 36.0; }
+
+LatDesc make_desc(const lb_params& p, uint64_t base) {
+  LatDesc L;
+  std::memset(&L, 0, sizeof(L));
+  L.base = base;
+  L.plane = sites_of(p);
+  L.nsites = (uint32_t)L.plane;
+  L.nx = p.nx; L.ny = p.ny; L.nz = p.nz;
+  L.nxy = (uint32_t)p.nx * (uint32_t)p.ny;
+  L.wx = p.nx - 1;
+  L.wy = (uint32_t)(p.ny - 1) * (uint32_t)p.nx;
+  L.wz = (uint32_t)(p.nz - 1) * L.nxy;
+  div_magic(p.nx, L.dx_m, L.dx_s1, L.dx_s2);
+  div_magic(p.ny, L.dy_m, L.dy_s1, L.dy_s2);
+  L.key0 = (uint32_t)p.seed;
+  L.key1 = (uint32_t)(p.seed >> 32);
+  L.thermal = p.kT > 0.0 ? 1u : 0u;
+  L.rho0 = (float)p.rho0;
+  const double mu = 3.0 * p.kT;  // kT / c_s^2 in lattice units
+  for (int k = 4; k < Q; ++k) {
+    double g;
+    if (k == 4) g = p.gamma_bulk;
+    else if (k <= 9) g = p.gamma_shear;
+    else if (k <= 15) g = p.gamma_odd;
+    else g = p.gamma_even;
+    const bool noisy = (k <= 9) || p.thermal_modes == LB_THERMAL_ALL;
+    L.ca[k - 4] = (float)(g / (36.0 * wk(k)));
+    if (k <= 9) L.cb[k - 4] = (float)((1.0 - g) / (36.0 * wk(k)));
+    L.cc[k - 4] = noisy ? (float)std::sqrt(mu * (1.0 - g * g) / (wk(k) * p.rho0)) : 0.0f;
+  }
+  for (int k = 0; k < Q; ++k) L.ci[k] = (float)std::sqrt(mu / (p.rho0 * wk(k)));
+  return L;
+}
+
+bool is_wide(const lb_params& p) { return sites_of(p) * elem_size(p.storage) > (1ull << 32); }
+
+// ---------------------------------------------------------------- kernel tables
+template <int S, int P, bool W>
+void* step_ptr_b(int block) {
+  switch (block) {
+    case 64: return (void*)&k_step<S, P, W, 64>;
+    case 128: return (void*)&k_step<S, P, W, 128>;
+    case 256: return (void*)&k_step<S, P, W, 256>;
+    case 512: return (void*)&k_step<S, P, W, 512>;
+  }
+  return nullptr;
+}
+template <int S, int P>
+void* step_ptr_w(bool wide, int block) {
+  return wide ? step_ptr_b<S, P, true>(block) : step_ptr_b<S, P, false>(block);
+}
+template <int S>
+void* step_ptr_p(int parity, bool wide, int block) {
+  return parity ? step_ptr_w<S, 1>(wide, block) : step_ptr_w<S, 0>(wide, block);
+}
+void* step_ptr(int storage, int parity, bool wide, int block) {
+  switch (storage) {
+    case LB_F32: return step_ptr_p<ST_F32>(parity, wide, block);
+    case LB_F16: return step_ptr_p<ST_F16>(parity, wide, block);
+    case LB_BF16: return step_ptr_p<ST_BF16>(parity, wide, block);
+  }
+  return nullptr;
+}
+
+enum KernelKind { KK_INIT, KK_GATHER, KK_CHECK };
+template <int S, int P, bool W>
+void* aux_ptr3(KernelKind kk) {
+  switch (kk) {
+    case KK_INIT: return (void*)&k_init<S, P, W>;
+    case KK_GATHER: return (void*)&k_gather<S, P, W>;
+    case KK_CHECK: return (void*)&k_check<S, P, W>;
+  }
+  return nullptr;
+}
+template <int S, int P>
+void* aux_ptr2(KernelKind kk, bool wide) { return wide ? aux_ptr3<S, P, true>(kk) : aux_ptr3<S, P, false>(kk); }
+template <int S>
+void* aux_ptr1(KernelKind kk, int parity, bool wide) {
+  return parity ? aux_ptr2<S, 1>(kk, wide) : aux_ptr2<S, 0>(kk, wide);
+}
+void* aux_ptr(KernelKind kk, int storage, int parity, bool wide) {
+  switch (storage) {
+    case LB_F32: return aux_ptr1<ST_F32>(kk, parity, wide);
+    case LB_F16: return aux_ptr1<ST_F16>(kk, parity, wide);
+    case LB_BF16: return aux_ptr1<ST_BF16>(kk, parity, wide);
+  }
+  return nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+struct lb_ctx {
+  bool owner = true;            // false for views
+  lb_ctx* parent = nullptr;     // batch of a view
+  int replica = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int storage = LB_F32;
+  bool wide = false;
+  std::vector<lb_params> reps;  // one per lattice (1 for a single lattice)
+  std::vector<uint64_t> offsets;
+  int64_t t = 0;                // host mirror of *d_t
+
+  // device metadata: [d_t (8 B) | result (5 doubles) | pad] [partials] [lats] [lats in tile order] [blk]
+  char* d_meta = nullptr;
+  uint64_t* d_t = nullptr;
+  double* d_result = nullptr;
+  double* d_partial = nullptr;
+  LatDesc* d_lats = nullptr;
+  LatDesc* d_tile_lats = nullptr;
+  uint32_t* d_blk = nullptr;
+  double* h_result = nullptr;   // pinned
+  std::vector<LatDesc> lats;
+
+  lb_schedule sched{256, 0, 1, 16};
+  uint32_t grid = 0;            // blocks per step
+
+  // graph of sched.graph_chunk steps starting at even t, plus the counter advance
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  struct StepArgs {
+    const LatDesc* lats;
+    const uint32_t* blk;
+    uint32_t nlat;
+    uint32_t remap;
+    const uint64_t* d_t;
+    uint32_t t_off;
+  };
+  std::vector<StepArgs> graph_args;
+  struct AdvArgs {
+    uint64_t* d_t;
+    uint64_t n;
+  } adv_args;
+
+  lb_ctx* root() { return parent ? parent : this; }
+};
+
+namespace {
+
+void drop_graph(lb_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
+// Tile order and per-lattice block prefix for the current schedule.
+int upload_schedule(lb_ctx* c) {
+  const int nlat = (int)c->lats.size();
+  std::vector<int> order(nlat);
+  for (int i = 0; i < nlat; ++i) order[i] = i;
+  if (c->sched.order == 1)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return c->lats[a].nsites > c->lats[b].nsites; });
+  else if (c->sched.order == 2)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return c->lats[a].nsites < c->lats[b].nsites; });
+  std::vector<LatDesc> tl(nlat);
+  std::vector<uint32_t> blk(nlat + 1);
+  uint64_t acc = 0;
+  for (int i = 0; i < nlat; ++i) {
+    tl[i] = c->lats[order[i]];
+    blk[i] = (uint32_t)acc;
+    acc += (c->lats[order[i]].nsites + c->sched.block - 1) / c->sched.block;
+  }
+  if (acc >= (1ull << 31)) return fail(LB_EUNSUPPORTED, "too many workgroups for one launch");
+  blk[nlat] = (uint32_t)acc;
+  c->grid = (uint32_t)acc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(c->d_tile_lats, tl.data(), sizeof(LatDesc) * nlat, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_blk, blk.data(), sizeof(uint32_t) * (nlat + 1), hipMemcpyHostToDevice));
+  drop_graph(c);
+  return LB_OK;
+}
+
+int launch_step(lb_ctx* c, uint32_t t_off, int parity) {
+  void* fn = step_ptr(c->storage, parity, c->wide, c->sched.block);
+  if (!fn) return fail(LB_EINVAL, "no step kernel for this schedule");
+  lb_ctx::StepArgs a{c->d_tile_lats, c->d_blk, (uint32_t)c->lats.size(), (uint32_t)c->sched.xcd_remap,
+                     c->d_t, t_off};
+  void* args[] = {&a.lats, &a.blk, &a.nlat, &a.remap, &a.d_t, &a.t_off};
+  HIP_TRY(hipLaunchKernel(fn, dim3(c->grid), dim3(c->sched.block), args, 0, c->stream));
+  return LB_OK;
+}
+
+int launch_advance(lb_ctx* c, uint64_t n) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->d_t, n);
+  HIP_TRY(hipGetLastError());
+  return LB_OK;
+}
+
+int build_graph(lb_ctx* c) {
+  drop_graph(c);
+  const int K = c->sched.graph_chunk;
+  HIP_TRY(hipGraphCreate(&c->graph, 0));
+  c->graph_args.assign(K, {});
+  hipGraphNode_t prev = nullptr;
+  for (int s = 0; s < K; ++s) {
+    c->graph_args[s] = {c->d_tile_lats, c->d_blk, (uint32_t)c->lats.size(), (uint32_t)c->sched.xcd_remap,
+                        c->d_t, (uint32_t)s};
+    lb_ctx::StepArgs& a = c->graph_args[s];
+    void* args[] = {&a.lats, &a.blk, &a.nlat, &a.remap, &a.d_t, &a.t_off};
+    hipKernelNodeParams kp{};
+    kp.func = step_ptr(c->storage, s & 1, c->wide, c->sched.block);
+    kp.gridDim = dim3(c->grid);
+    kp.blockDim = dim3(c->sched.block);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node;
+    HIP_TRY(hipGraphAddKernelNode(&node, c->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+    prev = node;
+  }
+  c->adv_args = {c->d_t, (uint64_t)K};
+  void* aargs[] = {&c->adv_args.d_t, &c->adv_args.n};
+  hipKernelNodeParams kp{};
+  kp.func = (void*)&k_advance;
+  kp.gridDim = dim3(1);
+  kp.blockDim = dim3(64);
+  kp.kernelParams = aargs;
+  hipGraphNode_t node;
+  HIP_TRY(hipGraphAddKernelNode(&node, c->graph, &prev, 1, &kp));
+  HIP_TRY(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  return LB_OK;
+}
+
+int direct_steps(lb_ctx* c, int64_t m) {
+  for (int64_t s = 0; s < m; ++s) {
+    int rc = launch_step(c, (uint32_t)s, (int)((c->t + s) & 1));
+    if (rc) return rc;
+  }
+  int rc = launch_advance(c, (uint64_t)m);
+  if (rc) return rc;
+  c->t += m;
+  return LB_OK;
+}
+
+int advance(lb_ctx* c, int64_t n) {
+  if (n < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+  HIP_TRY(hipSetDevice(c->device));
+  const int K = c->sched.graph_chunk;
+  if (n > 0 && (c->t & 1)) {
+    int rc = direct_steps(c, 1);
+    if (rc) return rc;
+    --n;
+  }
+  if (n >= K) {
+    if (!c->graph_exec) {
+      int rc = build_graph(c);
+      if (rc) return rc;
+    }
+    while (n >= K) {
+      HIP_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+      c->t += K;
+      n -= K;
+    }
+  }
+  if (n > 0) return direct_steps(c, n);
+  return LB_OK;
+}
+
+int alloc_meta(lb_ctx* c) {
+  const int nlat = (int)c->lats.size();
+  const size_t head = 256;
+  const size_t part = sizeof(double) * 5 * CHECK_BLOCKS;
+  const size_t lats = sizeof(LatDesc) * nlat;
+  const size_t blk = sizeof(uint32_t) * (nlat + 1);
+  auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
+  const size_t total = head + up(part) + 2 * up(lats) + up(blk);
+  HIP_TRY(hipMalloc(&c->d_meta, total));
+  c->d_t = reinterpret_cast<uint64_t*>(c->d_meta);
+  c->d_result = reinterpret_cast<double*>(c->d_meta + 64);
+  c->d_partial = reinterpret_cast<double*>(c->d_meta + head);
+  c->d_lats = reinterpret_cast<LatDesc*>(c->d_meta + head + up(part));
+  c->d_tile_lats = reinterpret_cast<LatDesc*>(c->d_meta + head + up(part) + up(lats));
+  c->d_blk = reinterpret_cast<uint32_t*>(c->d_meta + head + up(part) + 2 * up(lats));
+  HIP_TRY(hipHostMalloc((void**)&c->h_result, sizeof(double) * 5, hipHostMallocDefault));
+  HIP_TRY(hipMemcpy(c->d_lats, c->lats.data(), lats, hipMemcpyHostToDevice));
+  return LB_OK;
+}
+
+void free_ctx(lb_ctx* c) {
+  if (!c) return;
+  if (c->owner) {
+    drop_graph(c);
+    if (c->d_meta) (void)hipFree(c->d_meta);
+    if (c->h_result) (void)hipHostFree(c->h_result);
+  }
+  delete c;
+}
+
+int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity) {
+  const lb_params& p = c->reps[idx];
+  const uint32_t n = (uint32_t)sites_of(p);
+  void* fn = aux_ptr(KK_INIT, c->storage, parity, c->wide);
+  const LatDesc* L = c->d_lats + idx;
+  int k = kind;
+  const float* f = d_fields;
+  void* args[] = {&L, &k, &f};
+  HIP_TRY(hipLaunchKernel(fn, dim3((n + 255) / 256), dim3(256), args, 0, c->stream));
+  return LB_OK;
+}
+
+int default_schedule(lb_ctx* c) {
+  c->sched = lb_schedule{256, 0, 1, 16};
+  return upload_schedule(c);
+}
+
+// Local view of one lattice for gathers: (ctx owning the metadata, index).
+struct View {
+  lb_ctx* root;
+  int idx;
+};
+View view_of(lb_ctx* c) { return c->parent ? View{c->parent, c->replica} : View{c, 0}; }
+
+int gather(lb_ctx* c, int what, float* d_out) {
+  if (!c) return fail(LB_EINVAL, "ctx is NULL");
+  if (!d_out) return fail(LB_EINVAL, "output pointer is NULL");
+  View v = view_of(c);
+  lb_ctx* r = v.root;
+  if (r->reps.size() > 1 && !c->parent) return fail(LB_EINVAL, "gathers on a batch need a view (lb_batch_view)");
+  HIP_TRY(hipSetDevice(r->device));
+  const uint32_t n = (uint32_t)sites_of(r->reps[v.idx]);
+  void* fn = aux_ptr(KK_GATHER, r->storage, (int)(r->t & 1), r->wide);
+  const LatDesc* L = r->d_lats + v.idx;
+  int w = what;
+  float* o = d_out;
+  void* args[] = {&L, &w, &o};
+  HIP_TRY(hipLaunchKernel(fn, dim3((n + 255) / 256), dim3(256), args, 0, r->stream));
+  return LB_OK;
+}
+
+}  // namespace
+
+// ================================================================ C ABI
+extern "C" {
+
+size_t lb_state_bytes(const lb_params* p) {
+  if (validate(p) != LB_OK) return 0;
+  return (size_t)(19 * sites_of(*p) * elem_size(p->storage));
+}
+
+const char* lb_strerror(int code) {
+  switch (code) {
+    case LB_OK: return "success";
+    case LB_EINVAL: return "invalid argument";
+    case LB_EDEVICE: return "HIP device or launch failure";
+    case LB_ESTATE: return "state holds non-finite populations or rho <= 0";
+    case LB_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+const char* lb_last_error(void) { return g_last_error.c_str(); }
+
+int lb_init(const lb_params* p, void* d_state, void* hip_stream, int32_t init_kind, const float* d_fields,
+            int64_t t0, lb_ctx** out) {
+  if (!out) return fail(LB_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate(p);
+  if (rc) return rc;
+  if (!d_state) return fail(LB_EINVAL, "d_state is NULL");
+  if (((uintptr_t)d_state & 255) != 0) return fail(LB_EINVAL, "d_state must be 256-byte aligned");
+  if (init_kind < LB_INIT_REST || init_kind > LB_INIT_KEEP) return fail(LB_EINVAL, "unknown init_kind");
+  if (init_kind == LB_INIT_FIELDS && !d_fields) return fail(LB_EINVAL, "LB_INIT_FIELDS needs d_fields");
+  if (t0 < 0) return fail(LB_EINVAL, "t0 must be >= 0");
+
+  lb_ctx* c = new lb_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(LB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  }
+  c->storage = p->storage;
+  c->wide = is_wide(*p);
+  c->reps.push_back(*p);
+  c->offsets.push_back(0);
+  c->lats.push_back(make_desc(*p, (uint64_t)(uintptr_t)d_state));
+  c->t = t0;
+  if ((rc = alloc_meta(c)) || (rc = default_schedule(c))) {
+    free_ctx(c);
+    return rc;
+  }
+  hipLaunchKernelGGL(k_set_t, dim3(1), dim3(64), 0, c->stream, c->d_t, (uint64_t)t0);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return fail(LB_EDEVICE, std::string("k_set_t: ") + hipGetErrorString(e));
+  }
+  if (init_kind != LB_INIT_KEEP && (rc = init_lattice(c, 0, init_kind, d_fields, (int)(t0 & 1)))) {
+    free_ctx(c);
+    return rc;
+  }
+  *out = c;
+  return LB_OK;
+}
+
+int lb_step(lb_ctx* ctx, int64_t nsteps) {
+  if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+  if (ctx->parent) return fail(LB_EINVAL, "a view cannot step; step its batch");
+  return advance(ctx, nsteps);
+}
+
+int lb_populations(lb_ctx* ctx, float* d_out) { return gather(ctx, 0, d_out); }
+int lb_moments(lb_ctx* ctx, float* d_out) { return gather(ctx, 1, d_out); }
+int lb_modes(lb_ctx* ctx, float* d_out) { return gather(ctx, 2, d_out); }
+
+int lb_check(lb_ctx* ctx, int64_t* n_bad, double* sums_out) {
+  if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+  View v = view_of(ctx);
+  lb_ctx* r = v.root;
+  if (r->reps.size() > 1 && !ctx->parent) return fail(LB_EINVAL, "lb_check on a batch needs a view");
+  HIP_TRY(hipSetDevice(r->device));
+  void* fn = aux_ptr(KK_CHECK, r->storage, (int)(r->t & 1), r->wide);
+  const LatDesc* L = r->d_lats + v.idx;
+  double* part = r->d_partial;
+  void* args[] = {&L, &part};
+  HIP_TRY(hipLaunchKernel(fn, dim3(CHECK_BLOCKS), dim3(256), args, 0, r->stream));
+  hipLaunchKernelGGL(k_check_final, dim3(1), dim3(64), 0, r->stream, r->d_partial, CHECK_BLOCKS, r->d_result);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(r->h_result, r->d_result, sizeof(double) * 5, hipMemcpyDeviceToHost, r->stream));
+  HIP_TRY(hipStreamSynchronize(r->stream));
+  const lb_params& p = r->reps[v.idx];
+  const int64_t bad = (int64_t)r->h_result[0];
+  if (n_bad) *n_bad = bad;
+  if (sums_out) {
+    sums_out[0] = r->h_result[1] + p.rho0 * (double)sites_of(p);
+    for (int a = 0; a < 3; ++a) sums_out[a + 1] = r->h_result[a + 2];
+  }
+  return bad > 0 ? fail(LB_ESTATE, "non-finite populations or rho <= 0 found") : LB_OK;
+}
+
+int64_t lb_step_count(const lb_ctx* ctx) {
+  if (!ctx) return -1;
+  return ctx->parent ? ctx->parent->t : ctx->t;
+}
+
+void lb_destroy(lb_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->owner) (void)hipStreamSynchronize(ctx->stream);
+  free_ctx(ctx);
+}
+
+size_t lb_batch_pool_bytes(const lb_params* reps, int32_t nrep) {
+  if (!reps || nrep < 1) return 0;
+  size_t total = 0;
+  for (int r = 0; r < nrep; ++r) {
+    size_t b = lb_state_bytes(&reps[r]);
+    if (!b) return 0;
+    total += (b + 255) & ~(size_t)255;
+  }
+  return total;
+}
+
+size_t lb_batch_offset(const lb_params* reps, int32_t nrep, int32_t r) {
+  if (!reps || r < 0 || r >= nrep) return 0;
+  size_t off = 0;
+  for (int i = 0; i < r; ++i) off += (lb_state_bytes(&reps[i]) + 255) & ~(size_t)255;
+  return off;
+}
+
+int lb_batch_init(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_stream, int32_t init_kind,
+                  int64_t t0, lb_ctx** out) {
+  if (!out) return fail(LB_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!reps || nrep < 1) return fail(LB_EINVAL, "need at least one replica");
+  for (int r = 0; r < nrep; ++r) {
+    int rc = validate(&reps[r]);
+    if (rc) return rc;
+    if (reps[r].storage != reps[0].storage) return fail(LB_EINVAL, "all replicas need the same storage type");
+    if (is_wide(reps[r])) return fail(LB_EUNSUPPORTED, "replicas must hold < 4 GiB per population plane");
+  }
+  if (!d_pool || ((uintptr_t)d_pool & 255)) return fail(LB_EINVAL, "d_pool must be non-NULL and 256-byte aligned");
+  if (init_kind == LB_INIT_FIELDS) return fail(LB_EUNSUPPORTED, "LB_INIT_FIELDS is not available for ensembles");
+  if (init_kind < LB_INIT_REST || init_kind > LB_INIT_KEEP) return fail(LB_EINVAL, "unknown init_kind");
+  if (t0 < 0) return fail(LB_EINVAL, "t0 must be >= 0");
+
+  lb_ctx* c = new lb_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  hipError_t e = hipGetDevice(&c->device);
+  if (e != hipSuccess) {
+    delete c;
+    return fail(LB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  }
+  c->storage = reps[0].storage;
+  c->wide = false;
+  for (int r = 0; r < nrep; ++r) {
+    const uint64_t off = lb_batch_offset(reps, nrep, r);
+    c->reps.push_back(reps[r]);
+    c->offsets.push_back(off);
+    c->lats.push_back(make_desc(reps[r], (uint64_t)(uintptr_t)d_pool + off));
+  }
+  c->t = t0;
+  int rc;
+  if ((rc = alloc_meta(c)) || (rc = default_schedule(c))) {
+    free_ctx(c);
+    return rc;
+  }
+  hipLaunchKernelGGL(k_set_t, dim3(1), dim3(64), 0, c->stream, c->d_t, (uint64_t)t0);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return fail(LB_EDEVICE, std::string("k_set_t: ") + hipGetErrorString(e));
+  }
+  if (init_kind != LB_INIT_KEEP)
+    for (int r = 0; r < nrep; ++r)
+      if ((rc = init_lattice(c, r, init_kind, nullptr, (int)(t0 & 1)))) {
+        free_ctx(c);
+        return rc;
+      }
+  *out = c;
+  return LB_OK;
+}
+
+int lb_batch_step(lb_ctx* batch, int64_t nsteps) {
+  if (!batch) return fail(LB_EINVAL, "batch is NULL");
+  if (batch->parent) return fail(LB_EINVAL, "a view cannot step; step its batch");
+  return advance(batch, nsteps);
+}
+
+int lb_batch_view(lb_ctx* batch, int32_t replica, lb_ctx** view) {
+  if (!batch || !view) return fail(LB_EINVAL, "NULL argument");
+  *view = nullptr;
+  if (batch->parent) return fail(LB_EINVAL, "cannot take a view of a view");
+  if (replica < 0 || replica >= (int)batch->reps.size()) return fail(LB_EINVAL, "replica out of range");
+  lb_ctx* v = new lb_ctx();
+  v->owner = false;
+  v->parent = batch;
+  v->replica = replica;
+  v->stream = batch->stream;
+  v->device = batch->device;
+  v->storage = batch->storage;
+  *view = v;
+  return LB_OK;
+}
+
+int lb_get_schedule(const lb_ctx* ctx, lb_schedule* out) {
+  if (!ctx || !out) return fail(LB_EINVAL, "NULL argument");
+  *out = (ctx->parent ? ctx->parent : ctx)->sched;
+  return LB_OK;
+}
+
+int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s) {
+  if (!ctx || !s) return fail(LB_EINVAL, "NULL argument");
+  if (ctx->parent) return fail(LB_EINVAL, "set the schedule on the batch, not a view");
+  if (s->block != 64 && s->block != 128 && s->block != 256 && s->block != 512)
+    return fail(LB_EINVAL, "block must be 64, 128, 256 or 512");
+  if (s->order < 0 || s->order > 2) return fail(LB_EINVAL, "order must be 0, 1 or 2");
+  if (s->xcd_remap != 0 && s->xcd_remap != 1) return fail(LB_EINVAL, "xcd_remap must be 0 or 1");
+  if (s->graph_chunk < 2 || (s->graph_chunk & 1) || s->graph_chunk > 1024)
+    return fail(LB_EINVAL, "graph_chunk must be even and in [2, 1024]");
+  HIP_TRY(hipSetDevice(ctx->device));
+  ctx->sched = *s;
+  return upload_schedule(ctx);
+}
+
+int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
+  if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+  if (ctx->parent) return fail(LB_EINVAL, "tune the batch, not a view");
+  if (steps < 2) return fail(LB_EINVAL, "steps must be >= 2");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+
+  // scratch copy of the whole state and of the step counter
+  size_t bytes = 0;
+  for (size_t r = 0; r < ctx->reps.size(); ++r)
+    bytes = std::max<size_t>(bytes, ctx->offsets[r] + ((lb_state_bytes(&ctx->reps[r]) + 255) & ~(size_t)255));
+  char* scratch = nullptr;
+  HIP_TRY(hipMalloc(&scratch, bytes));
+  const uint64_t base0 = ctx->lats[0].base - ctx->offsets[0];
+  HIP_TRY(hipMemcpyAsync(scratch, (void*)(uintptr_t)base0, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+
+  const std::vector<LatDesc> saved_lats = ctx->lats;
+  const lb_schedule saved = ctx->sched;
+  const int64_t saved_t = ctx->t;
+  for (size_t r = 0; r < ctx->lats.size(); ++r) ctx->lats[r].base = (uint64_t)(uintptr_t)scratch + ctx->offsets[r];
+
+  std::string rep = "[";
+  lb_schedule best = saved;
+  double best_ms = 1e300;
+  int rc = LB_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(LB_EDEVICE, "hipEventCreate");
+  const int blocks[] = {64, 128, 256, 512};
+  const int norders = ctx->lats.size() > 1 ? 3 : 1;
+  bool first = true;
+  for (int bi = 0; bi < 4 && rc == LB_OK; ++bi)
+    for (int ord = 0; ord < norders && rc == LB_OK; ++ord)
+      for (int remap = 0; remap < 2 && rc == LB_OK; ++remap) {
+        ctx->sched = lb_schedule{blocks[bi], ord, remap, saved.graph_chunk};
+        if ((rc = upload_schedule(ctx))) break;
+        // warm-up, then time `steps` steps
+        if ((rc = advance(ctx, 2))) break;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { rc = fail(LB_EDEVICE, "hipEventRecord"); break; }
+        if ((rc = advance(ctx, steps))) break;
+        if (hipEventRecord(e1, ctx->stream) != hipSuccess) { rc = fail(LB_EDEVICE, "hipEventRecord"); break; }
+        if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(LB_EDEVICE, "hipEventSynchronize"); break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double per = ms / steps;
+        char buf[160];
+        std::snprintf(buf, sizeof(buf), "%s{\"block\":%d,\"order\":%d,\"xcd_remap\":%d,\"ms_per_step\":%.6f}",
+                      first ? "" : ",", blocks[bi], ord, remap, per);
+        rep += buf;
+        first = false;
+        if (per < best_ms) {
+          best_ms = per;
+          best = ctx->sched;
+        }
+      }
+  rep += "]";
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+
+  // restore the state pointers, step counter and device counter; apply the best schedule
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(scratch);
+  ctx->lats = saved_lats;
+  ctx->t = saved_t;
+  (void)hipMemcpy(ctx->d_lats, ctx->lats.data(), sizeof(LatDesc) * ctx->lats.size(), hipMemcpyHostToDevice);
+  hipLaunchKernelGGL(k_set_t, dim3(1), dim3(64), 0, ctx->stream, ctx->d_t, (uint64_t)saved_t);
+  ctx->sched = (rc == LB_OK) ? best : saved;
+  int rc2 = upload_schedule(ctx);
+  if (report && report_len) {
+    std::strncpy(report, rep.c_str(), report_len - 1);
+    report[report_len - 1] = 0;
+  }
+  return rc ? rc : rc2;
+}
+
+}  // extern "C"

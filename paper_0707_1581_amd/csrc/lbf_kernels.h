@@ -1,0 +1,432 @@
+// lbf_kernels.h -- gfx950 kernels of the fluctuating D3Q19 lattice Boltzmann
+// update (Duenweg, Schiller & Ladd, arXiv:0707.1581): the fused in-place
+// collide-and-stream step, initial states, parity-resolved gathers and the
+// health-check reduction.
+//
+// One thread per lattice site; all 19 populations of a site are loaded
+// before anything is stored, the mode transform, relaxation and noise stay in
+// VGPRs, and nothing goes through LDS.  The in-place update uses the AA access
+// pattern: a step at even t reads plane i at site r and writes the
+// post-collision population i to plane opp(i) at r; a step at odd t reads
+// plane j at r + c_j (which holds n_opp(j)(r)) and writes population j to
+// plane j at r + c_j.  Each thread therefore reads and writes the same 19
+// locations, and no two threads touch the same location, so one buffer
+// suffices and no synchronisation is needed inside a step.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbf_math.h"
+
+namespace lbf {
+
+enum { ST_F32 = 0, ST_F16 = 1, ST_BF16 = 2 };
+
+// ---------------------------------------------------------------- storage
+// The stored value is d_i = (n_i - a_i rho0) / (a_i rho0); 16-bit forms round
+// to nearest even on store, all arithmetic is fp32.
+template <int S> struct Codec;
+template <> struct Codec<ST_F32> {
+  using T = float;
+  static __device__ __forceinline__ float dec(T v) { return v; }
+  static __device__ __forceinline__ T enc(float x) { return x; }
+};
+template <> struct Codec<ST_F16> {
+  using T = _Float16;
+  static __device__ __forceinline__ float dec(T v) { return (float)v; }
+  static __device__ __forceinline__ T enc(float x) { return (_Float16)x; }
+};
+template <> struct Codec<ST_BF16> {
+  using T = uint16_t;
+  static __device__ __forceinline__ float dec(T v) { return __uint_as_float((uint32_t)v << 16); }
+  static __device__ __forceinline__ T enc(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+};
+
+// ---------------------------------------------------------------- lattice descriptor
+// One per lattice (a single lattice, or one replica of an ensemble); read by
+// every workgroup through scalar loads.
+struct alignas(16) LatDesc {
+  uint64_t base;      // device address of plane 0
+  uint64_t plane;     // elements per plane = nx * ny * nz
+  uint32_t nsites;    // = plane (< 2^32)
+  uint32_t nx, ny, nz;
+  uint32_t nxy;
+  uint32_t wx, wy, wz;              // nx - 1, (ny - 1) nx, (nz - 1) nx ny
+  uint32_t dx_m, dx_s1, dx_s2;      // division by nx: (t + ((n - t) >> s1)) >> s2, t = mulhi(n, m)
+  uint32_t dy_m, dy_s1, dy_s2;      // division by ny
+  uint32_t key0, key1;              // Philox key = seed
+  uint32_t thermal;                 // 1 when kT > 0
+  float rho0;
+  float ca[15];   // gamma_k / (36 w_k), k = 4..18
+  float cb[6];    // (1 - gamma_k) / (36 w_k), k = 4..9
+  float cc[15];   // sqrt(mu (1 - gamma_k^2) / (w_k rho0)), k = 4..18; 0 if unthermalised
+  float ci[19];   // sqrt(mu / (rho0 w_k)): thermal initial state
+};
+static_assert(sizeof(LatDesc) % 16 == 0, "LatDesc alignment");
+
+__device__ __forceinline__ uint32_t fastdiv(uint32_t n, uint32_t m, uint32_t s1, uint32_t s2) {
+  const uint32_t t = __umulhi(n, m);
+  return (t + ((n - t) >> s1)) >> s2;
+}
+
+// ---------------------------------------------------------------- Philox4x32-10
+// Salmon, Moraes, Dror & Shaw (SC'11): ten rounds of two 32x32->64 products
+// of counter words 0 and 2 with the published multipliers, feeding the high
+// halves through the key and the other two words; the key advances by the
+// published Weyl constants between rounds.
+__device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                         uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+// Four 24-bit uniforms from three words taken as one 96-bit big-endian number.
+__device__ __forceinline__ void chunks4(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t ch[4]) {
+  ch[0] = w0 >> 8;
+  ch[1] = ((w0 << 16) | (w1 >> 16)) & 0xFFFFFFu;
+  ch[2] = ((w1 << 8) | (w2 >> 24)) & 0xFFFFFFu;
+  ch[3] = w2 & 0xFFFFFFu;
+}
+
+// Box-Muller pair from chunks (a, b): u1 = (a + 1) 2^-24 in (0, 1],
+// u2 = b 2^-24; returns scale * sqrt(-2 ln u1) * (cos 2 pi u2, sin 2 pi u2).
+// v_log_f32 is log2 and v_sin/v_cos take revolutions.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float scale, float& z0, float& z1) {
+  const float u1 = __builtin_fmaf((float)a, 0x1p-24f, 0x1p-24f);
+  const float u2 = (float)b * 0x1p-24f;
+  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1)) * scale;
+  z0 = r * __builtin_amdgcn_cosf(u2);
+  z1 = r * __builtin_amdgcn_sinf(u2);
+}
+
+// ---------------------------------------------------------------- addressing
+// Element offsets o_j of site r + c_j (periodic), j = 0..18.
+template <class Off>
+__device__ __forceinline__ void neighbour_offsets(const LatDesc& L, uint32_t site, Off o[Q]) {
+  const uint32_t zy = fastdiv(site, L.dx_m, L.dx_s1, L.dx_s2);
+  const uint32_t x = site - zy * L.nx;
+  const uint32_t z = fastdiv(zy, L.dy_m, L.dy_s1, L.dy_s2);
+  const uint32_t y = zy - z * L.ny;
+  // signed steps in 32-bit wrap-around arithmetic; the sums land in [0, N)
+  const uint32_t xm = (x == 0) ? L.wx : 0xFFFFFFFFu;
+  const uint32_t xp = (x == L.wx) ? 0u - L.wx : 1u;
+  const uint32_t ym = (y == 0) ? L.wy : 0u - L.nx;
+  const uint32_t yp = (y * L.nx == L.wy) ? 0u - L.wy : L.nx;
+  const uint32_t zm = (z == 0) ? L.wz : 0u - L.nxy;
+  const uint32_t zp = (z * L.nxy == L.wz) ? 0u - L.wz : L.nxy;
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    uint32_t s = site;
+    if (CY[j] > 0) s += yp;
+    if (CY[j] < 0) s += ym;
+    if (CZ[j] > 0) s += zp;
+    if (CZ[j] < 0) s += zm;
+    if (CX[j] > 0) s += xp;
+    if (CX[j] < 0) s += xm;
+    o[j] = (Off)s;
+  }
+}
+
+// Global-memory (address space 1) access to plane `plane` at element offset o:
+// a uniform 64-bit plane base plus a per-lane byte offset, which the
+// compiler turns into the SGPR-base + VGPR-offset form of global_load/store
+// when the offset is 32-bit.
+#define LBF_GLOBAL __attribute__((address_space(1)))
+template <class T, class Off>
+__device__ __forceinline__ T ld(const LatDesc& L, int plane, Off o) {
+  const LBF_GLOBAL char* p = (const LBF_GLOBAL char*)(L.base + (uint64_t)plane * L.plane * sizeof(T));
+  return *(const LBF_GLOBAL T*)(p + (Off)(o * (Off)sizeof(T)));
+}
+template <class T, class Off>
+__device__ __forceinline__ void st(const LatDesc& L, int plane, Off o, T v) {
+  LBF_GLOBAL char* p = (LBF_GLOBAL char*)(L.base + (uint64_t)plane * L.plane * sizeof(T));
+  *(LBF_GLOBAL T*)(p + (Off)(o * (Off)sizeof(T))) = v;
+}
+
+// Load the 19 populations (as d_i) of site r of the state at parity P.
+template <int S, int P, class Off>
+__device__ __forceinline__ void load_site(const LatDesc& L, uint32_t site, float d[Q], Off o[Q]) {
+  using C = Codec<S>;
+  if (P == 0) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) o[j] = (Off)site;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = C::dec(ld<typename C::T>(L, i, o[i]));
+  } else {
+    neighbour_offsets(L, site, o);
+    // plane j at r + c_j holds population opp(j) of site r
+#pragma unroll
+    for (int j = 0; j < Q; ++j) d[OPP[j]] = C::dec(ld<typename C::T>(L, j, o[j]));
+  }
+}
+
+// ---------------------------------------------------------------- collision
+// Post-collision d*_i of one site from its pre-collision d_i, in place.
+// Equilibrium stress modes in units of rho0/36 (R = 36 rho / rho0):
+// mu_4 = |j|^2 / R, mu_5 = (2 jx^2 - jy^2 - jz^2) / R, mu_6 = (jy^2 - jz^2) / R,
+// mu_7..9 = jx jy / R, jy jz / R, jz jx / R (the stress modes of Eq.
+// derived_equil_distrib with sigma_2 = c_s^2 = 1/3; kinetic modes have none).
+__device__ __forceinline__ void collide(const LatDesc& L, float d[Q], uint32_t site, uint32_t tlo,
+                                        uint32_t thi) {
+  float mu[Q];
+  forward_modes(d, mu);
+
+  const float R = 36.0f + mu[0];
+  const float iR = __builtin_amdgcn_rcpf(R);
+  const float vx = mu[1] * iR, vy = mu[2] * iR, vz = mu[3] * iR;
+  const float xx = mu[1] * vx, yy = mu[2] * vy, zz = mu[3] * vz;
+  float eq[6];
+  eq[0] = (xx + yy) + zz;
+  eq[1] = (2.0f * xx - yy) - zz;
+  eq[2] = yy - zz;
+  eq[3] = mu[1] * vy;
+  eq[4] = mu[2] * vz;
+  eq[5] = mu[3] * vx;
+
+  float z[16];
+  if (L.thermal) {
+    // sqrt(rho / rho0) scales every noise amplitude (local density)
+    const float sig = __builtin_amdgcn_sqrtf(R * (1.0f / 36.0f));
+    uint32_t w[12];
+    philox10(site, tlo, 0u, thi, L.key0, L.key1, w);
+    philox10(site, tlo, 1u, thi, L.key0, L.key1, w + 4);
+    philox10(site, tlo, 2u, thi, L.key0, L.key1, w + 8);
+    uint32_t ch[16];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) chunks4(w[3 * g], w[3 * g + 1], w[3 * g + 2], ch + 4 * g);
+#pragma unroll
+    for (int p = 0; p < 8; ++p) box_muller(ch[2 * p], ch[2 * p + 1], sig, z[2 * p], z[2 * p + 1]);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) z[s] = 0.0f;
+  }
+
+  float nu[Q];
+  nu[0] = mu[0] * (1.0f / 36.0f);
+  nu[1] = mu[1] * (1.0f / 12.0f);
+  nu[2] = mu[2] * (1.0f / 12.0f);
+  nu[3] = mu[3] * (1.0f / 12.0f);
+#pragma unroll
+  for (int k = 4; k < 10; ++k)
+    nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], __builtin_fmaf(L.cb[k - 4], eq[k - 4], L.cc[k - 4] * z[k - 4]));
+#pragma unroll
+  for (int k = 10; k < Q; ++k) nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], L.cc[k - 4] * z[k - 4]);
+
+  back_transform(nu, d);
+}
+
+// ---------------------------------------------------------------- tile lookup
+// Blocks are dealt to the eight XCDs round-robin; the remap hands each XCD a
+// contiguous range of logical tiles so neighbouring tiles share an L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t i, uint32_t G) {
+  const uint32_t q = G >> 3, r = G & 7u, x = i & 7u, k = i >> 3;
+  return x * q + (x < r ? x : r) + k;
+}
+
+// Lattice of logical block b: blk[l] <= b < blk[l + 1] (uniform search).
+__device__ __forceinline__ uint32_t find_lattice(const uint32_t* __restrict__ blk, uint32_t nlat, uint32_t b) {
+  uint32_t lo = 0, hi = nlat;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (blk[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- step kernel
+// One fused collide-and-stream step at step count t = *d_t + t_off with
+// parity P = t & 1, for every site of every lattice in lats[0..nlat).
+template <int S, int P, bool WIDE, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
+       uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
+  using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  using C = Codec<S>;
+  const uint32_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  uint32_t l = 0;
+  if (nlat > 1) l = find_lattice(blk, nlat, b);
+  const LatDesc& L = lats[l];
+  const uint32_t b0 = (nlat > 1) ? blk[l] : 0u;
+  const uint32_t site = (b - b0) * BLOCK + threadIdx.x;
+  if (site >= L.nsites) return;
+  const uint64_t t = *d_t + t_off;
+
+  float d[Q];
+  Off o[Q];
+  load_site<S, P>(L, site, d, o);
+  collide(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
+  if (P == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st(L, OPP[i], o[i], C::enc(d[i]));
+  } else {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) st(L, j, o[j], C::enc(d[j]));
+  }
+}
+
+// Advance the device step counter after a run of step kernels.
+__global__ void k_advance(uint64_t* d_t, uint64_t n) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *d_t += n;
+}
+__global__ void k_set_t(uint64_t* d_t, uint64_t t) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *d_t = t;
+}
+
+// ---------------------------------------------------------------- initial states
+// Store the 19 d_i of site r as the state at parity P.
+template <int S, int P, class Off>
+__device__ __forceinline__ void store_site(const LatDesc& L, uint32_t site, const float d[Q]) {
+  using C = Codec<S>;
+  if (P == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st(L, i, (Off)site, C::enc(d[i]));
+  } else {
+    Off o[Q];
+    neighbour_offsets(L, site, o);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) st(L, j, o[j], C::enc(d[OPP[j]]));
+  }
+}
+
+// kind 0: rest; kind 1: thermal (stream 1, normal k -> mode k);
+// kind 2: n_i^eq(rho, u) from fields (4, nz, ny, nx).
+template <int S, int P, bool WIDE>
+__global__ void __launch_bounds__(256)
+k_init(const LatDesc* __restrict__ Lp, int kind, const float* __restrict__ fields) {
+  using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  const LatDesc& L = *Lp;
+  const uint32_t site = blockIdx.x * 256u + threadIdx.x;
+  if (site >= L.nsites) return;
+  float d[Q];
+  if (kind == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = 0.0f;
+  } else if (kind == 1) {
+    uint32_t w[16];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) philox10(site, 0u, (1u << 16) | (uint32_t)c, 0u, L.key0, L.key1, w + 4 * c);
+    uint32_t ch[20];
+#pragma unroll
+    for (int g = 0; g < 5; ++g) chunks4(w[3 * g], w[3 * g + 1], w[3 * g + 2], ch + 4 * g);
+    float z[20];
+#pragma unroll
+    for (int p = 0; p < 10; ++p) box_muller(ch[2 * p], ch[2 * p + 1], 1.0f, z[2 * p], z[2 * p + 1]);
+    float nu[Q];
+#pragma unroll
+    for (int k = 0; k < Q; ++k) nu[k] = L.ci[k] * z[k];
+    back_transform(nu, d);
+  } else {
+    const uint64_t N = L.plane;
+    const float rho = fields[site], ux = fields[N + site], uy = fields[2 * N + site], uz = fields[3 * N + site];
+    // d_i = rho/rho0 (1 + 3 u.c + 9/2 (u.c)^2 - 3/2 u^2) - 1
+    const float dr = rho / L.rho0 - 1.0f;
+    const float uu = 1.5f * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float uc = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+      const float poly = __builtin_fmaf(4.5f * uc, uc, 3.0f * uc) - uu;
+      d[i] = __builtin_fmaf(1.0f + dr, poly, dr);
+    }
+  }
+  store_site<S, P, Off>(L, site, d);
+}
+
+// ---------------------------------------------------------------- gathers
+// what: 0 populations n_i (19 planes), 1 moments rho, j (4 planes), 2 modes m_k (19 planes).
+template <int S, int P, bool WIDE>
+__global__ void __launch_bounds__(256)
+k_gather(const LatDesc* __restrict__ Lp, int what, float* __restrict__ out) {
+  using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  const LatDesc& L = *Lp;
+  const uint32_t site = blockIdx.x * 256u + threadIdx.x;
+  if (site >= L.nsites) return;
+  const uint64_t N = L.plane;
+  float d[Q];
+  Off o[Q];
+  load_site<S, P>(L, site, d, o);
+  if (what == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const float ar = (i == 0 ? (1.0f / 3.0f) : (i <= 6 ? (1.0f / 18.0f) : (1.0f / 36.0f))) * L.rho0;
+      out[i * N + site] = __builtin_fmaf(ar, d[i], ar);
+    }
+  } else {
+    float mu[Q];
+    forward_modes(d, mu);
+    const float s = L.rho0 * (1.0f / 36.0f);
+    if (what == 1) {
+      out[site] = __builtin_fmaf(s, mu[0], L.rho0);
+      out[N + site] = s * mu[1];
+      out[2 * N + site] = s * mu[2];
+      out[3 * N + site] = s * mu[3];
+    } else {
+#pragma unroll
+      for (int k = 0; k < Q; ++k) out[k * N + site] = s * mu[k];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- health check
+// Per-block partial sums (bad-site count, rho - rho0, jx, jy, jz) in fp64 over
+// a grid-stride loop; a second one-block kernel reduces the partials in a
+// fixed order, so the result is deterministic.
+constexpr int CHECK_BLOCKS = 512;
+template <int S, int P, bool WIDE>
+__global__ void __launch_bounds__(256)
+k_check(const LatDesc* __restrict__ Lp, double* __restrict__ partial) {
+  using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  const LatDesc& L = *Lp;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (uint32_t site = blockIdx.x * 256u + threadIdx.x; site < L.nsites; site += gridDim.x * 256u) {
+    float d[Q];
+    Off o[Q];
+    load_site<S, P>(L, site, d, o);
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) finite = finite && __builtin_isfinite(d[i]);
+    float mu[Q];
+    forward_modes(d, mu);
+    const float s = L.rho0 * (1.0f / 36.0f);
+    const float rho = __builtin_fmaf(s, mu[0], L.rho0);
+    if (!finite || !(rho > 0.0f)) acc[0] += 1.0;
+    acc[1] += (double)(s * mu[0]);
+    acc[2] += (double)(s * mu[1]);
+    acc[3] += (double)(s * mu[2]);
+    acc[4] += (double)(s * mu[3]);
+  }
+  __shared__ double red[5][256];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) red[c][threadIdx.x] = acc[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < (unsigned)w)
+#pragma unroll
+      for (int c = 0; c < 5; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) partial[blockIdx.x * 5 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(64) k_check_final(const double* __restrict__ partial, int nblocks,
+                                                    double* __restrict__ result) {
+  if (threadIdx.x < 5) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[b * 5 + threadIdx.x];
+    result[threadIdx.x] = s;
+  }
+}
+
+}  // namespace lbf

@@ -1,0 +1,308 @@
+"""Python binding of the C ABI in include/lbf.h (argument marshalling only).
+
+Every step of the update runs in the HIP kernels of ``liblbf.so``; torch is
+used for device memory and streams.  If the library has not been built, or
+no GPU is present, the calls raise: there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbf.so")
+
+LB_OK, LB_EINVAL, LB_EDEVICE, LB_ESTATE, LB_EUNSUPPORTED = 0, -1, -2, -3, -4
+STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
+STORAGE_DTYPE = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
+INIT = {"rest": 0, "thermal": 1, "fields": 2, "keep": 3}
+THERMAL_MODES = {"all": 0, "stress_only": 1}
+Q = 19
+
+
+class LbParams(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("storage", ctypes.c_int32),
+        ("rho0", ctypes.c_double), ("kT", ctypes.c_double),
+        ("gamma_bulk", ctypes.c_double), ("gamma_shear", ctypes.c_double),
+        ("gamma_odd", ctypes.c_double), ("gamma_even", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("thermal_modes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+    ]
+
+
+class LbSchedule(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32), ("graph_chunk", ctypes.c_int32)]
+
+
+# (name, restype, argtypes) of every entry point in include/lbf.h
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+SIGNATURES = [
+    ("lb_state_bytes", ctypes.c_size_t, [_P(LbParams)]),
+    ("lb_init", ctypes.c_int, [_P(LbParams), _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64, _P(_vp)]),
+    ("lb_step", ctypes.c_int, [_vp, ctypes.c_int64]),
+    ("lb_populations", ctypes.c_int, [_vp, _vp]),
+    ("lb_moments", ctypes.c_int, [_vp, _vp]),
+    ("lb_modes", ctypes.c_int, [_vp, _vp]),
+    ("lb_check", ctypes.c_int, [_vp, _P(ctypes.c_int64), _P(ctypes.c_double)]),
+    ("lb_step_count", ctypes.c_int64, [_vp]),
+    ("lb_destroy", None, [_vp]),
+    ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
+    ("lb_last_error", ctypes.c_char_p, []),
+    ("lb_batch_pool_bytes", ctypes.c_size_t, [_P(LbParams), ctypes.c_int32]),
+    ("lb_batch_offset", ctypes.c_size_t, [_P(LbParams), ctypes.c_int32, ctypes.c_int32]),
+    ("lb_batch_init", ctypes.c_int, [_P(LbParams), ctypes.c_int32, _vp, _vp, ctypes.c_int32,
+                                     ctypes.c_int64, _P(_vp)]),
+    ("lb_batch_step", ctypes.c_int, [_vp, ctypes.c_int64]),
+    ("lb_batch_view", ctypes.c_int, [_vp, ctypes.c_int32, _P(_vp)]),
+    ("lb_get_schedule", ctypes.c_int, [_vp, _P(LbSchedule)]),
+    ("lb_set_schedule", ctypes.c_int, [_vp, _P(LbSchedule)]),
+    ("lb_autotune", ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded liblbf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class LBError(RuntimeError):
+    def __init__(self, code, where):
+        L = lib()
+        msg = L.lb_last_error().decode()
+        super().__init__(f"{where}: {L.lb_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(rc, where):
+    if rc != LB_OK:
+        raise LBError(rc, where)
+
+
+def make_params(nx, ny, nz, storage="f32", rho0=1.0, kT=0.0, gamma_bulk=0.5, gamma_shear=0.5,
+                gamma_odd=0.0, gamma_even=0.0, seed=0, thermal_modes="all"):
+    return LbParams(int(nx), int(ny), int(nz), STORAGE[storage], float(rho0), float(kT),
+                    float(gamma_bulk), float(gamma_shear), float(gamma_odd), float(gamma_even),
+                    int(seed), THERMAL_MODES[thermal_modes], 0)
+
+
+def _stream_ptr(device, stream):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return ctypes.c_void_p(s.cuda_stream), s
+
+
+def _aligned(t):
+    if t.data_ptr() % 256:
+        raise ValueError("device buffers must be 256-byte aligned")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class _Gathers:
+    """Parity-resolved gathers shared by lattices and replica views."""
+
+    def _dims(self):
+        return self.nz, self.ny, self.nx
+
+    def populations(self):
+        out = torch.empty((Q, *self._dims()), dtype=torch.float32, device=self.device)
+        _check(lib().lb_populations(self._ctx, _aligned(out)), "lb_populations")
+        return out
+
+    def moments(self):
+        out = torch.empty((4, *self._dims()), dtype=torch.float32, device=self.device)
+        _check(lib().lb_moments(self._ctx, _aligned(out)), "lb_moments")
+        return out
+
+    def modes(self):
+        out = torch.empty((Q, *self._dims()), dtype=torch.float32, device=self.device)
+        _check(lib().lb_modes(self._ctx, _aligned(out)), "lb_modes")
+        return out
+
+    def check(self):
+        """(n_bad, [sum rho, sum jx, sum jy, sum jz]); raises on LB_ESTATE."""
+        n_bad = ctypes.c_int64(0)
+        sums = (ctypes.c_double * 4)()
+        rc = lib().lb_check(self._ctx, ctypes.byref(n_bad), sums)
+        if rc not in (LB_OK, LB_ESTATE):
+            _check(rc, "lb_check")
+        return int(n_bad.value), list(sums)
+
+    @property
+    def t(self):
+        return int(lib().lb_step_count(self._ctx))
+
+
+class Lattice(_Gathers):
+    """One periodic D3Q19 lattice; the state is a caller-owned torch tensor
+    (19, nz, ny, nx) of scaled deviations in the storage dtype."""
+
+    def __init__(self, nx, ny, nz, storage="f32", rho0=1.0, kT=0.0, gamma_bulk=0.5,
+                 gamma_shear=0.5, gamma_odd=0.0, gamma_even=0.0, seed=0, thermal_modes="all",
+                 init="rest", fields=None, t0=0, device="cuda", stream=None, state=None):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.storage = storage
+        self.params = make_params(nx, ny, nz, storage, rho0, kT, gamma_bulk, gamma_shear,
+                                  gamma_odd, gamma_even, seed, thermal_modes)
+        self.device = torch.device(device)
+        nbytes = lib().lb_state_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            raise LBError(LB_EINVAL, "lb_state_bytes")
+        shape = (Q, self.nz, self.ny, self.nx)
+        if state is None:
+            state = torch.empty(shape, dtype=STORAGE_DTYPE[storage], device=self.device)
+        if tuple(state.shape) != shape or state.dtype != STORAGE_DTYPE[storage] or not state.is_contiguous():
+            raise ValueError("state must be a contiguous (19, nz, ny, nx) tensor of the storage dtype")
+        self.state = state
+        f = None
+        if init == "fields":
+            if fields is None:
+                raise ValueError("init='fields' needs fields (4, nz, ny, nx)")
+            self._fields = fields.to(device=self.device, dtype=torch.float32).contiguous()
+            if tuple(self._fields.shape) != (4, self.nz, self.ny, self.nx):
+                raise ValueError("fields must be (4, nz, ny, nx)")
+            f = _aligned(self._fields)
+        sp, self.stream = _stream_ptr(self.device, stream)
+        ctx = ctypes.c_void_p()
+        _check(lib().lb_init(ctypes.byref(self.params), _aligned(self.state), sp, INIT[init], f,
+                             int(t0), ctypes.byref(ctx)), "lb_init")
+        self._ctx = ctx
+
+    def step(self, n=1):
+        _check(lib().lb_step(self._ctx, int(n)), "lb_step")
+
+    def schedule(self):
+        s = LbSchedule()
+        _check(lib().lb_get_schedule(self._ctx, ctypes.byref(s)), "lb_get_schedule")
+        return {"block": s.block, "order": s.order, "xcd_remap": s.xcd_remap, "graph_chunk": s.graph_chunk}
+
+    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16):
+        s = LbSchedule(block, order, xcd_remap, graph_chunk)
+        _check(lib().lb_set_schedule(self._ctx, ctypes.byref(s)), "lb_set_schedule")
+
+    def autotune(self, steps=10):
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().lb_autotune(self._ctx, int(steps), buf, len(buf)), "lb_autotune")
+        return buf.value.decode()
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().lb_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class ReplicaView(_Gathers):
+    def __init__(self, ens, r, ctx):
+        p = ens.params[r]
+        self.nx, self.ny, self.nz = p.nx, p.ny, p.nz
+        self.device = ens.device
+        self._ctx = ctx
+        self._ens = ens
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            lib().lb_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """Independent replicas (own box, rates, kT, seed; one storage type)
+    advanced together, one kernel launch per step for all of them."""
+
+    def __init__(self, replicas, storage="f32", init="thermal", t0=0, device="cuda", stream=None):
+        self.storage = storage
+        self.device = torch.device(device)
+        self.params = [make_params(storage=storage, **r) for r in replicas]
+        n = len(self.params)
+        self._arr = (LbParams * n)(*self.params)
+        nbytes = lib().lb_batch_pool_bytes(self._arr, n)
+        if nbytes == 0:
+            raise LBError(LB_EINVAL, "lb_batch_pool_bytes")
+        self.pool = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        sp, self.stream = _stream_ptr(self.device, stream)
+        ctx = ctypes.c_void_p()
+        _check(lib().lb_batch_init(self._arr, n, _aligned(self.pool), sp, INIT[init], int(t0),
+                                   ctypes.byref(ctx)), "lb_batch_init")
+        self._ctx = ctx
+        self._views = {}
+
+    def __len__(self):
+        return len(self.params)
+
+    def sites(self):
+        return sum(p.nx * p.ny * p.nz for p in self.params)
+
+    def step(self, n=1):
+        _check(lib().lb_batch_step(self._ctx, int(n)), "lb_batch_step")
+
+    @property
+    def t(self):
+        return int(lib().lb_step_count(self._ctx))
+
+    def view(self, r):
+        if r not in self._views:
+            v = ctypes.c_void_p()
+            _check(lib().lb_batch_view(self._ctx, int(r), ctypes.byref(v)), "lb_batch_view")
+            self._views[r] = ReplicaView(self, r, v)
+        return self._views[r]
+
+    def replica_state(self, r):
+        """The raw state tensor of replica r (a view into the pool)."""
+        p = self.params[r]
+        off = lib().lb_batch_offset(self._arr, len(self.params), int(r))
+        nbytes = lib().lb_state_bytes(ctypes.byref(p))
+        return self.pool[off:off + nbytes].view(STORAGE_DTYPE[self.storage]).view(Q, p.nz, p.ny, p.nx)
+
+    def schedule(self):
+        s = LbSchedule()
+        _check(lib().lb_get_schedule(self._ctx, ctypes.byref(s)), "lb_get_schedule")
+        return {"block": s.block, "order": s.order, "xcd_remap": s.xcd_remap, "graph_chunk": s.graph_chunk}
+
+    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16):
+        s = LbSchedule(block, order, xcd_remap, graph_chunk)
+        _check(lib().lb_set_schedule(self._ctx, ctypes.byref(s)), "lb_set_schedule")
+
+    def autotune(self, steps=10):
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib().lb_autotune(self._ctx, int(steps), buf, len(buf)), "lb_autotune")
+        return buf.value.decode()
+
+    def close(self):
+        for v in self._views.values():
+            v.close()
+        self._views = {}
+        if getattr(self, "_ctx", None):
+            lib().lb_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
