@@ -99,7 +99,9 @@ LatDesc make_desc(const lb_params& p, uint64_t base) {
   return L;
 }
 
-bool is_wide(const lb_params& p) { return sites_of(p) * elem_size(p.storage) > (1ull << 32); }
+// Planes of 4 GiB or more need 64-bit offsets (buffer descriptors hold a
+// 32-bit size).
+bool is_wide(const lb_params& p) { return sites_of(p) * elem_size(p.storage) >= (1ull << 32); }
 
 // ---------------------------------------------------------------- kernel tables
 template <int S, int P, bool W>

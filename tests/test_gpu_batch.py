@@ -1,0 +1,124 @@
+"""Ensembles: every replica of a batch, advanced by one launch per step for
+all replicas, is bit-identical to the same lattice run alone (the noise is
+keyed on the replica's own seed, site and step), under every schedule; and
+16-bit storage stays within its rounding of the FP64 oracle."""
+import json
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_0707_1581_amd as lbf
+import workloads
+from tests.gpu_util import gpu_pops, oracle_params, say, scaled_err
+
+pytestmark = pytest.mark.gpu
+
+REPS = [
+    dict(nx=16, ny=16, nz=16, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.5, gamma_odd=0.0,
+         gamma_even=0.0, seed=1),
+    dict(nx=5, ny=3, nz=7, rho0=1.0, kT=1e-3, gamma_bulk=0.2, gamma_shear=0.9, gamma_odd=0.3,
+         gamma_even=-0.3, seed=2),
+    dict(nx=1, ny=1, nz=1, rho0=1.3, kT=5e-4, gamma_bulk=0.0, gamma_shear=0.1, gamma_odd=0.0,
+         gamma_even=0.0, seed=3),
+    dict(nx=32, ny=8, nz=9, rho0=0.9, kT=1e-5, gamma_bulk=0.5, gamma_shear=-0.5, gamma_odd=0.0,
+         gamma_even=0.0, seed=4),
+    dict(nx=9, ny=9, nz=9, rho0=1.0, kT=0.0, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=0.0,
+         gamma_even=0.0, seed=5),
+    dict(nx=2, ny=30, nz=3, rho0=1.0, kT=2e-4, gamma_bulk=0.7, gamma_shear=0.3, gamma_odd=0.1,
+         gamma_even=0.2, seed=2 ** 36 + 9),
+]
+
+
+def standalone_states(reps, storage, steps):
+    out = []
+    for r in reps:
+        lat = lbf.Lattice(**r, storage=storage, init="thermal")
+        lat.step(steps)
+        out.append(lat.state.clone())
+        lat.close()
+    return out
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_batch_equals_standalone(storage):
+    steps = 13
+    say(f"batch vs standalone, {storage}")
+    want = standalone_states(REPS, storage, steps)
+    for sched in [dict(block=256, order=0, xcd_remap=1, graph_chunk=16),
+                  dict(block=64, order=1, xcd_remap=0, graph_chunk=4),
+                  dict(block=512, order=2, xcd_remap=1, graph_chunk=2)]:
+        ens = lbf.Ensemble(REPS, storage=storage, init="thermal")
+        ens.set_schedule(**sched)
+        ens.step(steps)
+        assert ens.t == steps
+        for r in range(len(REPS)):
+            assert torch.equal(ens.replica_state(r), want[r]), (sched, r)
+        ens.close()
+
+
+def test_batch_views_gather_and_check():
+    ens = lbf.Ensemble(REPS, init="thermal")
+    ens.step(5)
+    for r, cfg in enumerate(REPS):
+        v = ens.view(r)
+        p = oracle_params(cfg)
+        n = oracle.run(p, oracle.init(p, oracle.INIT_THERMAL), 0, 5)
+        assert scaled_err(gpu_pops(v), n, cfg["rho0"]) < 1e-5, r
+        np.testing.assert_allclose(v.moments().double().cpu().numpy(), oracle.moments(p, n), atol=2e-6)
+        nb, sums = v.check()
+        assert nb == 0
+        assert v.t == 5
+    ens.close()
+
+
+def test_autotune_leaves_state_and_counter_unchanged():
+    ens = lbf.Ensemble(REPS, init="thermal")
+    ens.step(3)
+    before = ens.pool.clone()
+    rep = json.loads(ens.autotune(steps=4))
+    assert len(rep) == 4 * 3 * 2 and all(c["ms_per_step"] > 0 for c in rep)
+    assert ens.t == 3
+    assert torch.equal(ens.pool, before)
+    ens.step(10)
+    want = standalone_states(REPS, "f32", 13)
+    for r in range(len(REPS)):
+        assert torch.equal(ens.replica_state(r), want[r]), r
+    ens.close()
+
+
+def test_ensemble_workload_runs():
+    """The 96-replica workload (sizes 32^3..96^3): a few steps, no bad sites,
+    and one replica against its standalone run."""
+    reps = workloads.ensemble_replicas()
+    ens = lbf.Ensemble(reps, init="thermal")
+    ens.step(6)
+    for r in (0, 47, 95):
+        nb, _ = ens.view(r).check()
+        assert nb == 0
+    lat = lbf.Lattice(**reps[47], init="thermal")
+    lat.step(6)
+    assert torch.equal(ens.replica_state(47), lat.state)
+    ens.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f16", 2e-3), ("bf16", 1.6e-2)])
+def test_16bit_storage_close_to_oracle(storage, tol):
+    """16-bit storage of d_i rounds every stored value to 11 (fp16) or 8
+    (bf16) significant bits, relative error 2^-11 / 2^-8 of |d_i| <~ 0.5
+    per store; over 5 steps the deviation stays within ~8 such roundings."""
+    cfg = dict(nx=12, ny=11, nz=10, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8,
+               gamma_odd=0.0, gamma_even=0.0, seed=1234)
+    p = oracle_params(cfg)
+    lat = lbf.Lattice(**cfg, storage=storage, init="thermal")
+    n = oracle.init(p, oracle.INIT_THERMAL)
+    err0 = scaled_err(gpu_pops(lat), n, 1.0)
+    lat.step(5)
+    n = oracle.run(p, n, 0, 5)
+    err5 = scaled_err(gpu_pops(lat), n, 1.0)
+    say(f"{storage}: init err {err0:.2e}, 5-step err {err5:.2e}")
+    assert err0 < tol / 4
+    assert err5 < tol
+    nb, sums = lat.check()
+    assert nb == 0
