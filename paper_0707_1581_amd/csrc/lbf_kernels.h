@@ -160,8 +160,9 @@ constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
 constexpr int RAW_BUFFER_WORD3 = 0x00020000;
 
 template <int S, int P> struct CachePolicy {
-  static constexpr int load = (P == 0 || S != ST_F32) ? CPOL_NT : 0;
-  static constexpr int store = (P == 0) ? CPOL_NT : 0;
+  // plane j of the odd step is accessed at r + c_j: shifted along x iff c_jx != 0
+  static constexpr bool nt_load(int j) { return P == 0 || CX[j] == 0; }
+  static constexpr bool nt_store(int j) { return P == 0 || CX[j] == 0; }
 };
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const LatDesc& L, int plane, uint32_t esize) {
@@ -217,6 +218,16 @@ __device__ __forceinline__ void st(const LatDesc& L, int plane, Off o, T v) {
   }
 }
 
+// Policy chosen per plane; `nt` is a constant once the plane loops unroll.
+template <class T, class Off>
+__device__ __forceinline__ T ld_sel(const LatDesc& L, int plane, Off o, bool nt) {
+  return nt ? ld<T, CPOL_NT>(L, plane, o) : ld<T, 0>(L, plane, o);
+}
+template <class T, class Off>
+__device__ __forceinline__ void st_sel(const LatDesc& L, int plane, Off o, T v, bool nt) {
+  if (nt) st<T, CPOL_NT>(L, plane, o, v); else st<T, 0>(L, plane, o, v);
+}
+
 // Load the 19 populations (as d_i) of site r of the state at parity P.
 template <int S, int P, class Off>
 __device__ __forceinline__ void load_site(const LatDesc& L, uint32_t site, float d[Q], Off o[Q]) {
@@ -225,12 +236,12 @@ __device__ __forceinline__ void load_site(const LatDesc& L, uint32_t site, float
 #pragma unroll
     for (int j = 0; j < Q; ++j) o[j] = (Off)site;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = C::dec(ld<typename C::T, CachePolicy<S, P>::load>(L, i, o[i]));
+    for (int i = 0; i < Q; ++i) d[i] = C::dec(ld_sel<typename C::T>(L, i, o[i], CachePolicy<S, P>::nt_load(i)));
   } else {
     neighbour_offsets(L, site, o);
     // plane j at r + c_j holds population opp(j) of site r
 #pragma unroll
-    for (int j = 0; j < Q; ++j) d[OPP[j]] = C::dec(ld<typename C::T, CachePolicy<S, P>::load>(L, j, o[j]));
+    for (int j = 0; j < Q; ++j) d[OPP[j]] = C::dec(ld_sel<typename C::T>(L, j, o[j], CachePolicy<S, P>::nt_load(j)));
   }
 }
 
@@ -331,10 +342,10 @@ k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint3
   collide(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
   if (P == 0) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st<typename C::T, CachePolicy<S, 0>::store>(L, OPP[i], o[i], C::enc(d[i]));
+    for (int i = 0; i < Q; ++i) st_sel(L, OPP[i], o[i], C::enc(d[i]), CachePolicy<S, 0>::nt_store(OPP[i]));
   } else {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) st<typename C::T, CachePolicy<S, 1>::store>(L, j, o[j], C::enc(d[j]));
+    for (int j = 0; j < Q; ++j) st_sel(L, j, o[j], C::enc(d[j]), CachePolicy<S, 1>::nt_store(j));
   }
 }
 
