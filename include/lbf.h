@@ -145,6 +145,20 @@ void lb_destroy(lb_ctx* ctx);
 const char* lb_strerror(int code);
 const char* lb_last_error(void);
 
+/* Lattice parameters from physical ones (Sec. VI, choice of parameters).
+ * Inputs, in one consistent unit system: lattice spacing b > 0, time step
+ * h > 0, mass density rho > 0, shear and bulk viscosities eta > 0 and
+ * zeta > 0, and k_B T >= 0.  With the D3Q19 sound speed c_s^2 = (1/3) b^2/h^2,
+ *   eta_hat  = eta h / (rho b^2 / 3),   gamma_shear = (2 eta_hat - 1) / (2 eta_hat + 1),
+ *   zeta_hat = zeta h / (rho b^2 / 3),  gamma_bulk  = (3 zeta_hat - 1) / (3 zeta_hat + 1),
+ *   mu = k_B T h^2 / ((1/3) b^5)  (mass per site per particle), and in lattice
+ * units (b = h = 1, mass unit rho b^3): rho0 = 1 and kT = mu / (3 rho) =
+ * k_B T h^2 / (rho b^5).  Writes rho0, kT, gamma_shear and gamma_bulk into
+ * *p and leaves its other fields as they are.  Returns LB_EINVAL for
+ * invalid inputs (nothing is written). */
+int lb_params_from_physical(double b, double h, double rho, double eta, double zeta, double kBT,
+                            lb_params* p);
+
 /* ---- ensembles: many independent lattices in one launch per step ---- */
 
 /* Bytes of the pool for nrep replicas: each replica's state rounded up to

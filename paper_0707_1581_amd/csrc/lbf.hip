@@ -512,6 +512,25 @@ void lb_destroy(lb_ctx* ctx) {
   free_ctx(ctx);
 }
 
+int lb_params_from_physical(double b, double h, double rho, double eta, double zeta, double kBT,
+                            lb_params* p) {
+  if (!p) return fail(LB_EINVAL, "params is NULL");
+  const double v[5] = {b, h, rho, eta, zeta};
+  for (double x : v)
+    if (!(x > 0.0) || !std::isfinite(x)) return fail(LB_EINVAL, "b, h, rho, eta and zeta must be finite and > 0");
+  if (!(kBT >= 0.0) || !std::isfinite(kBT)) return fail(LB_EINVAL, "k_B T must be finite and >= 0");
+  const double cs2_hat = 1.0 / 3.0;  // D3Q19, Sec. II
+  const double d = 3.0;
+  const double eta_hat = eta * h / (rho * b * b * cs2_hat);
+  const double zeta_hat = zeta * h / (rho * b * b * cs2_hat);
+  const double mu = kBT * h * h / (cs2_hat * std::pow(b, d + 2.0));  // Sec. VI
+  p->rho0 = 1.0;
+  p->kT = cs2_hat * mu / rho;  // lattice units: mass unit rho b^3, mu_lattice = mu / rho
+  p->gamma_shear = (2.0 * eta_hat - 1.0) / (2.0 * eta_hat + 1.0);
+  p->gamma_bulk = (d * zeta_hat - 1.0) / (d * zeta_hat + 1.0);
+  return LB_OK;
+}
+
 size_t lb_batch_pool_bytes(const lb_params* reps, int32_t nrep) {
   if (!reps || nrep < 1) return 0;
   size_t total = 0;

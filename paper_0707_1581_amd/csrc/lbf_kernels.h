@@ -81,9 +81,16 @@ __device__ __forceinline__ void philox10(uint32_t c0, uint32_t c1, uint32_t c2, 
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    // three-input xor (truth table 0x96) in one gfx950 bitop3
-    const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
-    const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+    uint32_t n0, n2;
+    if (r == 0) {
+      // counter words 1..3 are uniform here: plain xors stay on the scalar unit
+      n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+      n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+    } else {
+      // three-input xor (truth table 0x96) in one gfx950 bitop3
+      n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, k0, 0x96);
+      n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, k1, 0x96);
+    }
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
@@ -103,15 +110,18 @@ __device__ __forceinline__ void chunks4(uint32_t w0, uint32_t w1, uint32_t w2, u
 }
 
 // Box-Muller pair from chunks (a, b): u1 = (a + 1) 2^-24 in (0, 1],
-// u2 = b 2^-24; returns scale * sqrt(-2 ln u1) * (cos 2 pi u2, sin 2 pi u2).
-// v_log_f32 is log2 and v_sin/v_cos take revolutions.
-__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float scale, float& z0, float& z1) {
+// u2 = b 2^-24; returns s * sqrt(-2 ln u1) * (cos 2 pi u2, sin 2 pi u2) with
+// s = sqrt(scale2): the caller passes -2 ln(2) s^2 as k2, folding the scale
+// into the log multiplier.  v_log_f32 is log2 and v_sin/v_cos take
+// revolutions.
+__device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float k2, float& z0, float& z1) {
   const float u1 = __builtin_fmaf((float)a, 0x1p-24f, 0x1p-24f);
   const float u2 = (float)b * 0x1p-24f;
-  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1)) * scale;
+  const float r = __builtin_amdgcn_sqrtf(k2 * __builtin_amdgcn_logf(u1));
   z0 = r * __builtin_amdgcn_cosf(u2);
   z1 = r * __builtin_amdgcn_sinf(u2);
 }
+constexpr float NEG_2LN2 = -1.3862943611198906f;  // -2 ln 2: sqrt(-2 ln u) = sqrt(-2 ln2 log2 u)
 
 // ---------------------------------------------------------------- addressing
 // Element offsets o_j of site r + c_j (periodic), j = 0..18.
@@ -268,10 +278,14 @@ __device__ __forceinline__ void collide(const LatDesc& L, float d[Q], uint32_t s
   eq[4] = mu[2] * vz;
   eq[5] = mu[3] * vx;
 
-  float z[16];
+  float nu[Q];
+  nu[0] = mu[0] * (1.0f / 36.0f);
+  nu[1] = mu[1] * (1.0f / 12.0f);
+  nu[2] = mu[2] * (1.0f / 12.0f);
+  nu[3] = mu[3] * (1.0f / 12.0f);
   if (L.thermal) {
-    // sqrt(rho / rho0) scales every noise amplitude (local density)
-    const float sig = __builtin_amdgcn_sqrtf(R * (1.0f / 36.0f));
+    // every noise amplitude scales with sqrt(rho / rho0) = sqrt(R / 36)
+    const float k2 = (NEG_2LN2 / 36.0f) * R;
     uint32_t w[12];
     philox10(site, tlo, 0u, thi, L.key0, L.key1, w);
     philox10(site, tlo, 1u, thi, L.key0, L.key1, w + 4);
@@ -279,23 +293,20 @@ __device__ __forceinline__ void collide(const LatDesc& L, float d[Q], uint32_t s
     uint32_t ch[16];
 #pragma unroll
     for (int g = 0; g < 4; ++g) chunks4(w[3 * g], w[3 * g + 1], w[3 * g + 2], ch + 4 * g);
+    float z[16];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) box_muller(ch[2 * p], ch[2 * p + 1], sig, z[2 * p], z[2 * p + 1]);
+    for (int p = 0; p < 8; ++p) box_muller(ch[2 * p], ch[2 * p + 1], k2, z[2 * p], z[2 * p + 1]);
+#pragma unroll
+    for (int k = 4; k < 10; ++k)
+      nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], __builtin_fmaf(L.cb[k - 4], eq[k - 4], L.cc[k - 4] * z[k - 4]));
+#pragma unroll
+    for (int k = 10; k < Q; ++k) nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], L.cc[k - 4] * z[k - 4]);
   } else {
 #pragma unroll
-    for (int s = 0; s < 16; ++s) z[s] = 0.0f;
+    for (int k = 4; k < 10; ++k) nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], L.cb[k - 4] * eq[k - 4]);
+#pragma unroll
+    for (int k = 10; k < Q; ++k) nu[k] = L.ca[k - 4] * mu[k];
   }
-
-  float nu[Q];
-  nu[0] = mu[0] * (1.0f / 36.0f);
-  nu[1] = mu[1] * (1.0f / 12.0f);
-  nu[2] = mu[2] * (1.0f / 12.0f);
-  nu[3] = mu[3] * (1.0f / 12.0f);
-#pragma unroll
-  for (int k = 4; k < 10; ++k)
-    nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], __builtin_fmaf(L.cb[k - 4], eq[k - 4], L.cc[k - 4] * z[k - 4]));
-#pragma unroll
-  for (int k = 10; k < Q; ++k) nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], L.cc[k - 4] * z[k - 4]);
 
   back_transform(nu, d);
 }
@@ -395,7 +406,7 @@ k_init(const LatDesc* __restrict__ Lp, int kind, const float* __restrict__ field
     for (int g = 0; g < 5; ++g) chunks4(w[3 * g], w[3 * g + 1], w[3 * g + 2], ch + 4 * g);
     float z[20];
 #pragma unroll
-    for (int p = 0; p < 10; ++p) box_muller(ch[2 * p], ch[2 * p + 1], 1.0f, z[2 * p], z[2 * p + 1]);
+    for (int p = 0; p < 10; ++p) box_muller(ch[2 * p], ch[2 * p + 1], NEG_2LN2, z[2 * p], z[2 * p + 1]);
     float nu[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) nu[k] = L.ci[k] * z[k];

@@ -52,6 +52,7 @@ SIGNATURES = [
     ("lb_destroy", None, [_vp]),
     ("lb_strerror", ctypes.c_char_p, [ctypes.c_int]),
     ("lb_last_error", ctypes.c_char_p, []),
+    ("lb_params_from_physical", ctypes.c_int, [ctypes.c_double] * 6 + [_P(LbParams)]),
     ("lb_batch_pool_bytes", ctypes.c_size_t, [_P(LbParams), ctypes.c_int32]),
     ("lb_batch_offset", ctypes.c_size_t, [_P(LbParams), ctypes.c_int32, ctypes.c_int32]),
     ("lb_batch_init", ctypes.c_int, [_P(LbParams), ctypes.c_int32, _vp, _vp, ctypes.c_int32,
@@ -99,6 +100,15 @@ def make_params(nx, ny, nz, storage="f32", rho0=1.0, kT=0.0, gamma_bulk=0.5, gam
     return LbParams(int(nx), int(ny), int(nz), STORAGE[storage], float(rho0), float(kT),
                     float(gamma_bulk), float(gamma_shear), float(gamma_odd), float(gamma_even),
                     int(seed), THERMAL_MODES[thermal_modes], 0)
+
+
+def physical_params(b, h, rho, eta, zeta, kBT):
+    """Lattice rho0, kT, gamma_shear, gamma_bulk from physical spacing, time
+    step, density, viscosities and k_B T (Sec. VI), via the C ABI."""
+    p = make_params(1, 1, 1)
+    _check(lib().lb_params_from_physical(b, h, rho, eta, zeta, kBT, ctypes.byref(p)),
+           "lb_params_from_physical")
+    return dict(rho0=p.rho0, kT=p.kT, gamma_shear=p.gamma_shear, gamma_bulk=p.gamma_bulk)
 
 
 def _stream_ptr(device, stream):

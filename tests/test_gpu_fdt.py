@@ -1,0 +1,71 @@
+"""Fluctuation-dissipation at the hydrodynamic level (Sec. V, Eqs. ce11-ce12
+with the noise covariance of Eq. macrostressfluct and k_B T = m_p c_s^2,
+Eq. mpeos): in equilibrium, the time correlation of a transverse momentum
+mode j_x(q) decays exactly as a deterministic perturbation does (the same
+linearised one-step operator L(q) = diag(exp(-i q.c)) M^-1 Gamma M), and its
+equal-time value is fixed by equipartition:
+
+    C(tau) = <j(q, t + tau) j(q, t)^*> = N mu rho0 c^T L(q)^tau A c,
+    C(0)   = N rho0 kT,
+
+with A = diag(a_i) (populations are independent with variance mu rho0 a_i
+in the stationary law) and c the velocity component of the mode."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_0707_1581_amd as lbf
+from tests import lbtheory as th
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+def test_transverse_momentum_correlation():
+    L, kT, gs, gb = 32, 1e-4, 0.5, 0.5
+    mu = 3 * kT
+    cfg = dict(nx=L, ny=L, nz=L, rho0=1.0, kT=kT, gamma_bulk=gb, gamma_shear=gs, gamma_odd=0.0,
+               gamma_even=0.0, seed=31337)
+    lat = lbf.Lattice(**cfg, init="thermal")
+    N = L ** 3
+    n_q = 1
+    q = 2 * np.pi * n_q / L
+    ph = torch.exp(-1j * q * torch.arange(L, device="cuda", dtype=torch.float64))
+    # six transverse (component, wave-vector axis) pairs; moments layout (rho, jx, jy, jz)[z][y][x]
+    pairs = [(1, 0), (2, 0), (1, 1), (3, 1), (2, 2), (3, 2)]  # (j component, axis z=0 y=1 x=2)
+    T, every = 16000, 2
+    series = []
+    lat.step(50)
+    for s in range(T // every):
+        lat.step(every)
+        m = lat.moments().double()
+        row = []
+        for comp, axis in pairs:
+            dims = tuple(d for d in (0, 1, 2) if d != axis)
+            prof = m[comp].sum(dim=dims)
+            row.append((prof * ph).sum())
+        series.append(torch.stack(row))
+    lat.close()
+    J = torch.stack(series).cpu().numpy()  # (samples, 6) complex
+    taus = np.arange(0, 41, 4)  # in steps; multiples of `every`
+    lags = taus // every
+    nb = 8
+    blocks = np.array_split(np.arange(J.shape[0]), nb)
+    meas = np.zeros((nb, len(taus)))
+    for b, idx in enumerate(blocks):
+        x = J[idx]
+        for k, lg in enumerate(lags):
+            meas[b, k] = np.mean(np.real(x[lg:] * np.conj(x[:len(x) - lg])))
+    C = meas.mean(axis=0)
+    se = meas.std(axis=0, ddof=1) / np.sqrt(nb)
+
+    c, a, e, w = oracle.tables()
+    Lop = th.one_step_operator([0, 0, q], th.mode_gammas(gb, gs, 0.0, 0.0), c, a, e, w)
+    cx = c[:, 0].astype(float)
+    pred = np.array([np.real(cx @ np.linalg.matrix_power(Lop, int(t)) @ (a * cx)) for t in taus]) * N * mu
+    say(f"C(0) measured {C[0]:.4e} vs N rho0 kT {N * kT:.4e}")
+    for t, cm, s, p in zip(taus, C, se, pred):
+        say(f"  tau={t:3d}: C/C0 pred {p / pred[0]:.4f} measured {cm / C[0]:.4f} (se {s / C[0]:.4f})")
+        assert abs(cm - p) < 5 * s + 0.02 * pred[0], (t, cm, p, s)
+    assert C[0] == pytest.approx(N * kT, rel=0.05)
