@@ -325,7 +325,8 @@ def main():
     roofline = {"bound": "hbm", "achieved": main_run["achieved_gbs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": main_run["achieved_gbs"] / HBM_PEAK_GBS,
                 "traffic": traffic,
-                "kernel": "lbf::k_step<fp32> (even and odd AA launches; mean launch duration)",
+                "kernel": "fp32 step kernel (lbf::k_step / lbf::k_step_rows as scheduled; even and odd "
+                          "AA launches; mean launch duration)",
                 "alg_bytes_per_launch": main_run["alg_bytes_per_launch"]}
     line = {
         "metric": "MLUPS and % HBM roofline, FP32 vs 16-bit storage at 1% mode-variance error",

@@ -186,20 +186,29 @@ int lb_batch_view(lb_ctx* batch, int32_t replica, lb_ctx** view);
 /* ---- launch schedule and autotuning ---- */
 
 typedef struct {
-  int32_t block;      /* threads per workgroup: 64, 128, 256 or 512          */
-  int32_t order;      /* tile order: 0 replica order, 1 largest replica      */
-                      /* first, 2 round-robin interleave of replicas         */
-  int32_t xcd_remap;  /* 1: give each XCD a contiguous range of tiles        */
-  int32_t graph_chunk;/* steps per graph replay (>= 2, even)                 */
+  int32_t block;        /* threads per workgroup: 64, 128, 256 or 512          */
+  int32_t order;        /* tile order: 0 replica order, 1 largest replica      */
+                        /* first, 2 smallest replica first                     */
+  int32_t graph_chunk;  /* steps per graph replay (>= 2, even)                 */
+  int32_t xcd_remap[2]; /* per step parity [even, odd]: 1 gives each XCD a     */
+                        /* contiguous range of tiles                           */
+  int32_t tiling[2];    /* per step parity: 0 each workgroup takes `block`     */
+                        /* consecutive sites; 1 each workgroup takes one       */
+                        /* `block`-long segment of one x-row, so y/z offsets   */
+                        /* are uniform (planes below 4 GiB, else               */
+                        /* LB_EUNSUPPORTED)                                    */
 } lb_schedule;
 
 int lb_get_schedule(const lb_ctx* ctx, lb_schedule* out);
 int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
 
 /* Time every candidate schedule on a scratch copy of the state (the state
- * and step count of ctx are unchanged), apply the fastest, and write a JSON
- * report (one object per candidate with its mean step time) into report
- * (NUL-terminated, truncated to report_len).  steps >= 2 per candidate. */
+ * and step count of ctx are unchanged): for each block size and tile order,
+ * every (xcd_remap, tiling) pair is timed on even and on odd steps
+ * separately (`steps` >= 2 launches of each parity), and the fastest pair is
+ * kept per parity.  Applies the best schedule and writes a JSON report (one
+ * object per candidate with its mean even and odd step times) into report
+ * (NUL-terminated, truncated to report_len). */
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
 
 #ifdef __cplusplus

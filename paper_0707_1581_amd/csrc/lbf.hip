@@ -131,6 +131,28 @@ void* step_ptr(int storage, int parity, bool wide, int block) {
   return nullptr;
 }
 
+// Row-tiled step kernels (non-wide lattices only).
+template <int S, int P>
+void* rows_ptr_b(int block) {
+  switch (block) {
+    case 64: return (void*)&k_step_rows<S, P, 64>;
+    case 128: return (void*)&k_step_rows<S, P, 128>;
+    case 256: return (void*)&k_step_rows<S, P, 256>;
+    case 512: return (void*)&k_step_rows<S, P, 512>;
+  }
+  return nullptr;
+}
+template <int S>
+void* rows_ptr_p(int parity, int block) { return parity ? rows_ptr_b<S, 1>(block) : rows_ptr_b<S, 0>(block); }
+void* rows_ptr(int storage, int parity, int block) {
+  switch (storage) {
+    case LB_F32: return rows_ptr_p<ST_F32>(parity, block);
+    case LB_F16: return rows_ptr_p<ST_F16>(parity, block);
+    case LB_BF16: return rows_ptr_p<ST_BF16>(parity, block);
+  }
+  return nullptr;
+}
+
 enum KernelKind { KK_INIT, KK_GATHER, KK_CHECK };
 template <int S, int P, bool W>
 void* aux_ptr3(KernelKind kk) {
@@ -179,11 +201,13 @@ struct lb_ctx {
   LatDesc* d_lats = nullptr;
   LatDesc* d_tile_lats = nullptr;
   uint32_t* d_blk = nullptr;
+  uint32_t* d_blk_rows = nullptr;   // tile prefix of the row tiling
   double* h_result = nullptr;   // pinned
   std::vector<LatDesc> lats;
 
-  lb_schedule sched{256, 0, 1, 16};
+  lb_schedule sched{256, 0, 16, {0, 0}, {1, 0}};
   uint32_t grid = 0;            // blocks per step
+  uint32_t grid_rows = 0;       // blocks per step with the row tiling
 
   // graph of sched.graph_chunk steps starting at even t, plus the counter advance
   hipGraph_t graph = nullptr;
@@ -226,30 +250,50 @@ int upload_schedule(lb_ctx* c) {
     std::stable_sort(order.begin(), order.end(),
                      [&](int a, int b) { return c->lats[a].nsites < c->lats[b].nsites; });
   std::vector<LatDesc> tl(nlat);
-  std::vector<uint32_t> blk(nlat + 1);
-  uint64_t acc = 0;
+  std::vector<uint32_t> blk(nlat + 1), blk_rows(nlat + 1);
+  uint64_t acc = 0, acc_rows = 0;
   for (int i = 0; i < nlat; ++i) {
     tl[i] = c->lats[order[i]];
+    tl[i].segs = (tl[i].nx + c->sched.block - 1) / c->sched.block;
+    div_magic(tl[i].segs, tl[i].ds_m, tl[i].ds_s1, tl[i].ds_s2);
     blk[i] = (uint32_t)acc;
+    blk_rows[i] = (uint32_t)acc_rows;
     acc += (c->lats[order[i]].nsites + c->sched.block - 1) / c->sched.block;
+    acc_rows += (uint64_t)tl[i].ny * tl[i].nz * tl[i].segs;
   }
-  if (acc >= (1ull << 31)) return fail(LB_EUNSUPPORTED, "too many workgroups for one launch");
+  if (acc >= (1ull << 31) || acc_rows >= (1ull << 31)) return fail(LB_EUNSUPPORTED, "too many workgroups for one launch");
   blk[nlat] = (uint32_t)acc;
+  blk_rows[nlat] = (uint32_t)acc_rows;
   c->grid = (uint32_t)acc;
+  c->grid_rows = (uint32_t)acc_rows;
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(c->d_tile_lats, tl.data(), sizeof(LatDesc) * nlat, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_blk, blk.data(), sizeof(uint32_t) * (nlat + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_blk_rows, blk_rows.data(), sizeof(uint32_t) * (nlat + 1), hipMemcpyHostToDevice));
   drop_graph(c);
   return LB_OK;
 }
 
+// Kernel, grid, workgroup size and tile prefix of a step of the given parity.
+struct StepLaunch {
+  void* fn;
+  uint32_t grid;
+  int block;
+  const uint32_t* blk;
+};
+StepLaunch step_launch(const lb_ctx* c, int parity) {
+  if (c->sched.tiling[parity])
+    return {rows_ptr(c->storage, parity, c->sched.block), c->grid_rows, c->sched.block, c->d_blk_rows};
+  return {step_ptr(c->storage, parity, c->wide, c->sched.block), c->grid, c->sched.block, c->d_blk};
+}
+
 int launch_step(lb_ctx* c, uint32_t t_off, int parity) {
-  void* fn = step_ptr(c->storage, parity, c->wide, c->sched.block);
-  if (!fn) return fail(LB_EINVAL, "no step kernel for this schedule");
-  lb_ctx::StepArgs a{c->d_tile_lats, c->d_blk, (uint32_t)c->lats.size(), (uint32_t)c->sched.xcd_remap,
+  const StepLaunch sl = step_launch(c, parity);
+  if (!sl.fn) return fail(LB_EINVAL, "no step kernel for this schedule");
+  lb_ctx::StepArgs a{c->d_tile_lats, sl.blk, (uint32_t)c->lats.size(), (uint32_t)c->sched.xcd_remap[parity],
                      c->d_t, t_off};
   void* args[] = {&a.lats, &a.blk, &a.nlat, &a.remap, &a.d_t, &a.t_off};
-  HIP_TRY(hipLaunchKernel(fn, dim3(c->grid), dim3(c->sched.block), args, 0, c->stream));
+  HIP_TRY(hipLaunchKernel(sl.fn, dim3(sl.grid), dim3(sl.block), args, 0, c->stream));
   return LB_OK;
 }
 
@@ -266,14 +310,16 @@ int build_graph(lb_ctx* c) {
   c->graph_args.assign(K, {});
   hipGraphNode_t prev = nullptr;
   for (int s = 0; s < K; ++s) {
-    c->graph_args[s] = {c->d_tile_lats, c->d_blk, (uint32_t)c->lats.size(), (uint32_t)c->sched.xcd_remap,
+    const StepLaunch sl = step_launch(c, s & 1);
+    if (!sl.fn) return fail(LB_EINVAL, "no step kernel for this schedule");
+    c->graph_args[s] = {c->d_tile_lats, sl.blk, (uint32_t)c->lats.size(), (uint32_t)c->sched.xcd_remap[s & 1],
                         c->d_t, (uint32_t)s};
     lb_ctx::StepArgs& a = c->graph_args[s];
     void* args[] = {&a.lats, &a.blk, &a.nlat, &a.remap, &a.d_t, &a.t_off};
     hipKernelNodeParams kp{};
-    kp.func = step_ptr(c->storage, s & 1, c->wide, c->sched.block);
-    kp.gridDim = dim3(c->grid);
-    kp.blockDim = dim3(c->sched.block);
+    kp.func = sl.fn;
+    kp.gridDim = dim3(sl.grid);
+    kp.blockDim = dim3(sl.block);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
     kp.extra = nullptr;
@@ -336,7 +382,7 @@ int alloc_meta(lb_ctx* c) {
   const size_t lats = sizeof(LatDesc) * nlat;
   const size_t blk = sizeof(uint32_t) * (nlat + 1);
   auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
-  const size_t total = head + up(part) + 2 * up(lats) + up(blk);
+  const size_t total = head + up(part) + 2 * up(lats) + 2 * up(blk);
   HIP_TRY(hipMalloc(&c->d_meta, total));
   c->d_t = reinterpret_cast<uint64_t*>(c->d_meta);
   c->d_result = reinterpret_cast<double*>(c->d_meta + 64);
@@ -344,6 +390,7 @@ int alloc_meta(lb_ctx* c) {
   c->d_lats = reinterpret_cast<LatDesc*>(c->d_meta + head + up(part));
   c->d_tile_lats = reinterpret_cast<LatDesc*>(c->d_meta + head + up(part) + up(lats));
   c->d_blk = reinterpret_cast<uint32_t*>(c->d_meta + head + up(part) + 2 * up(lats));
+  c->d_blk_rows = reinterpret_cast<uint32_t*>(c->d_meta + head + up(part) + 2 * up(lats) + up(blk));
   HIP_TRY(hipHostMalloc((void**)&c->h_result, sizeof(double) * 5, hipHostMallocDefault));
   HIP_TRY(hipMemcpy(c->d_lats, c->lats.data(), lats, hipMemcpyHostToDevice));
   return LB_OK;
@@ -371,8 +418,14 @@ int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity
   return LB_OK;
 }
 
+// Default schedule, from measurements on MI355X (512^3 box): fp32 runs the
+// even step row-tiled and the odd step flat, both without XCD remapping; the
+// 16-bit forms run both parities row-tiled with remapping.  lb_autotune
+// refines it for a given workload.
 int default_schedule(lb_ctx* c) {
-  c->sched = lb_schedule{256, 0, 1, 16};
+  if (c->storage == LB_F32) c->sched = lb_schedule{256, 0, 16, {0, 0}, {1, 0}};
+  else c->sched = lb_schedule{256, 0, 16, {1, 1}, {1, 1}};
+  if (c->wide) c->sched.tiling[0] = c->sched.tiling[1] = 0;
   return upload_schedule(c);
 }
 
@@ -636,9 +689,14 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s) {
   if (s->block != 64 && s->block != 128 && s->block != 256 && s->block != 512)
     return fail(LB_EINVAL, "block must be 64, 128, 256 or 512");
   if (s->order < 0 || s->order > 2) return fail(LB_EINVAL, "order must be 0, 1 or 2");
-  if (s->xcd_remap != 0 && s->xcd_remap != 1) return fail(LB_EINVAL, "xcd_remap must be 0 or 1");
+  for (int q = 0; q < 2; ++q) {
+    if (s->xcd_remap[q] != 0 && s->xcd_remap[q] != 1) return fail(LB_EINVAL, "xcd_remap entries must be 0 or 1");
+    if (s->tiling[q] != 0 && s->tiling[q] != 1) return fail(LB_EINVAL, "tiling entries must be 0 or 1");
+    if (s->tiling[q] && ctx->wide) return fail(LB_EUNSUPPORTED, "the row tiling needs planes below 4 GiB");
+  }
   if (s->graph_chunk < 2 || (s->graph_chunk & 1) || s->graph_chunk > 1024)
     return fail(LB_EINVAL, "graph_chunk must be even and in [2, 1024]");
+
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->sched = *s;
   return upload_schedule(ctx);
@@ -669,38 +727,65 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   lb_schedule best = saved;
   double best_ms = 1e300;
   int rc = LB_OK;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = fail(LB_EDEVICE, "hipEventCreate");
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  for (auto& e : ev)
+    if (rc == LB_OK && hipEventCreate(&e) != hipSuccess) rc = fail(LB_EDEVICE, "hipEventCreate");
   const int blocks[] = {64, 128, 256, 512};
   const int norders = ctx->lats.size() > 1 ? 3 : 1;
+  const int ntiling = ctx->wide ? 1 : 2;
   bool first = true;
+  // For each block size and tile order, time every (remap, tiling) pair on
+  // even and on odd steps separately and keep the fastest pair per parity;
+  // the state layout does not depend on the schedule, so the parities can
+  // be chosen independently.
   for (int bi = 0; bi < 4 && rc == LB_OK; ++bi)
-    for (int ord = 0; ord < norders && rc == LB_OK; ++ord)
-      for (int remap = 0; remap < 2 && rc == LB_OK; ++remap) {
-        ctx->sched = lb_schedule{blocks[bi], ord, remap, saved.graph_chunk};
-        if ((rc = upload_schedule(ctx))) break;
-        // warm-up, then time `steps` steps
-        if ((rc = advance(ctx, 2))) break;
-        if (hipEventRecord(e0, ctx->stream) != hipSuccess) { rc = fail(LB_EDEVICE, "hipEventRecord"); break; }
-        if ((rc = advance(ctx, steps))) break;
-        if (hipEventRecord(e1, ctx->stream) != hipSuccess) { rc = fail(LB_EDEVICE, "hipEventRecord"); break; }
-        if (hipEventSynchronize(e1) != hipSuccess) { rc = fail(LB_EDEVICE, "hipEventSynchronize"); break; }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const double per = ms / steps;
-        char buf[160];
-        std::snprintf(buf, sizeof(buf), "%s{\"block\":%d,\"order\":%d,\"xcd_remap\":%d,\"ms_per_step\":%.6f}",
-                      first ? "" : ",", blocks[bi], ord, remap, per);
-        rep += buf;
-        first = false;
-        if (per < best_ms) {
-          best_ms = per;
-          best = ctx->sched;
+    for (int ord = 0; ord < norders && rc == LB_OK; ++ord) {
+      double par_best[2] = {1e300, 1e300};
+      int par_remap[2] = {0, 0}, par_tiling[2] = {0, 0};
+      for (int remap = 0; remap < 2 && rc == LB_OK; ++remap)
+        for (int til = 0; til < ntiling && rc == LB_OK; ++til) {
+          ctx->sched = lb_schedule{blocks[bi], ord, saved.graph_chunk, {remap, remap}, {til, til}};
+          if ((rc = upload_schedule(ctx))) break;
+          if ((rc = direct_steps(ctx, 2))) break;  // warm-up
+          double par_ms[2] = {0.0, 0.0};
+          for (int k = 0; k < 2 * steps && rc == LB_OK; ++k) {
+            const int parity = (int)(ctx->t & 1);
+            if (hipEventRecord(ev[0], ctx->stream) != hipSuccess) { rc = fail(LB_EDEVICE, "hipEventRecord"); break; }
+            if ((rc = launch_step(ctx, 0, parity))) break;
+            if (hipEventRecord(ev[1], ctx->stream) != hipSuccess) { rc = fail(LB_EDEVICE, "hipEventRecord"); break; }
+            if ((rc = launch_advance(ctx, 1))) break;
+            ctx->t += 1;
+            if (hipEventSynchronize(ev[1]) != hipSuccess) { rc = fail(LB_EDEVICE, "hipEventSynchronize"); break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+            par_ms[parity] += ms;
+          }
+          if (rc) break;
+          for (int q = 0; q < 2; ++q) {
+            par_ms[q] /= steps;
+            if (par_ms[q] < par_best[q]) {
+              par_best[q] = par_ms[q];
+              par_remap[q] = remap;
+              par_tiling[q] = til;
+            }
+          }
+          char buf[200];
+          std::snprintf(buf, sizeof(buf),
+                        "%s{\"block\":%d,\"order\":%d,\"xcd_remap\":%d,\"tiling\":%d,"
+                        "\"even_ms\":%.6f,\"odd_ms\":%.6f}",
+                        first ? "" : ",", blocks[bi], ord, remap, til, par_ms[0], par_ms[1]);
+          rep += buf;
+          first = false;
         }
+      if (rc == LB_OK && par_best[0] + par_best[1] < best_ms) {
+        best_ms = par_best[0] + par_best[1];
+        best = lb_schedule{blocks[bi], ord, saved.graph_chunk, {par_remap[0], par_remap[1]},
+                           {par_tiling[0], par_tiling[1]}};
       }
+    }
   rep += "]";
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
 
   // restore the state pointers, step counter and device counter; apply the best schedule
   (void)hipStreamSynchronize(ctx->stream);

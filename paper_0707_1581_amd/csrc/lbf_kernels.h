@@ -57,6 +57,8 @@ struct alignas(16) LatDesc {
   uint32_t dy_m, dy_s1, dy_s2;      // division by ny
   uint32_t key0, key1;              // Philox key = seed
   uint32_t thermal;                 // 1 when kT > 0
+  uint32_t segs;                    // row tiling: workgroups per x-row (ceil(nx / block))
+  uint32_t ds_m, ds_s1, ds_s2;      // division by segs
   float rho0;
   float ca[15];   // gamma_k / (36 w_k), k = 4..18
   float cb[6];    // (1 - gamma_k) / (36 w_k), k = 4..9
@@ -182,28 +184,30 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const LatDesc& L, i
 }
 
 template <class T> struct Raw;
+// b: per-lane byte offset; so: uniform byte offset (the instruction's SGPR
+// offset field).
 template <> struct Raw<float> {
-  template <int POL> static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t b) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, b, 0, POL));
+  template <int POL> static __device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t r, uint32_t b, uint32_t so = 0) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, b, so, POL));
   }
-  template <int POL> static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t b, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, b, 0, POL);
+  template <int POL> static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t b, float v, uint32_t so = 0) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, b, so, POL);
   }
 };
 template <> struct Raw<_Float16> {
-  template <int POL> static __device__ __forceinline__ _Float16 ld(__amdgpu_buffer_rsrc_t r, uint32_t b) {
-    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, b, 0, POL));
+  template <int POL> static __device__ __forceinline__ _Float16 ld(__amdgpu_buffer_rsrc_t r, uint32_t b, uint32_t so = 0) {
+    return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, b, so, POL));
   }
-  template <int POL> static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t b, _Float16 v) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, b, 0, POL);
+  template <int POL> static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t b, _Float16 v, uint32_t so = 0) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, b, so, POL);
   }
 };
 template <> struct Raw<uint16_t> {
-  template <int POL> static __device__ __forceinline__ uint16_t ld(__amdgpu_buffer_rsrc_t r, uint32_t b) {
-    return __builtin_amdgcn_raw_buffer_load_b16(r, b, 0, POL);
+  template <int POL> static __device__ __forceinline__ uint16_t ld(__amdgpu_buffer_rsrc_t r, uint32_t b, uint32_t so = 0) {
+    return __builtin_amdgcn_raw_buffer_load_b16(r, b, so, POL);
   }
-  template <int POL> static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t b, uint16_t v) {
-    __builtin_amdgcn_raw_buffer_store_b16(v, r, b, 0, POL);
+  template <int POL> static __device__ __forceinline__ void st(__amdgpu_buffer_rsrc_t r, uint32_t b, uint16_t v, uint32_t so = 0) {
+    __builtin_amdgcn_raw_buffer_store_b16(v, r, b, so, POL);
   }
 };
 
@@ -357,6 +361,86 @@ k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint3
   } else {
 #pragma unroll
     for (int j = 0; j < Q; ++j) st_sel(L, j, o[j], C::enc(d[j]), CachePolicy<S, 1>::nt_store(j));
+  }
+}
+
+// ---------------------------------------------------------------- step kernel, row tiling
+// The same update with a different work split: each workgroup covers one
+// segment of BLOCK consecutive sites of one x-row (L.segs segments per row).
+// Then y, z, the periodic y/z neighbour rows and every plane's row offset are
+// uniform across the workgroup and live in SGPRs (they enter the buffer
+// instruction as its scalar offset); each lane only computes x and its two
+// periodic x-neighbours.  Lanes past the end of the row stay idle, so this
+// suits rows of at least a few workgroups' worth of sites.
+template <int S, int P, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
+            uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
+  using C = Codec<S>;
+  using T = typename C::T;
+  constexpr uint32_t ES = sizeof(T);
+  const uint32_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  uint32_t l = 0;
+  if (nlat > 1) l = find_lattice(blk, nlat, b);
+  const LatDesc& L = lats[l];
+  const uint32_t bl = b - ((nlat > 1) ? blk[l] : 0u);
+  // uniform: row (y + ny z) and segment of this workgroup
+  const uint32_t row = fastdiv(bl, L.ds_m, L.ds_s1, L.ds_s2);
+  const uint32_t x = (bl - row * L.segs) * BLOCK + threadIdx.x;
+  if (x >= L.nx) return;
+  const uint32_t z = fastdiv(row, L.dy_m, L.dy_s1, L.dy_s2);
+  const uint32_t y = row - z * L.ny;
+  const uint64_t t = *d_t + t_off;
+  const uint32_t site = x + row * L.nx;
+
+  // uniform row offsets (elements) of the y/z neighbours, periodic
+  const uint32_t r0 = row * L.nx;
+  const uint32_t ym = (y == 0) ? L.wy : 0u - L.nx;
+  const uint32_t yp = (y * L.nx == L.wy) ? 0u - L.wy : L.nx;
+  const uint32_t zm = (z == 0) ? L.wz : 0u - L.nxy;
+  const uint32_t zp = (z * L.nxy == L.wz) ? 0u - L.wz : L.nxy;
+  // per-lane x offsets in bytes: x - 1, x, x + 1 (periodic)
+  const uint32_t bx = x * ES;
+  const uint32_t bxm = (x == 0 ? L.wx : x - 1u) * ES;
+  const uint32_t bxp = (x == L.wx ? 0u : x + 1u) * ES;
+
+  float d[Q];
+  if (P == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      d[i] = C::dec(Raw<T>::template ld<CPOL_NT>(plane_rsrc(L, i, ES), bx, r0 * ES));
+  } else {
+    // plane j at r + c_j holds population opp(j) of site r
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      uint32_t ro = r0;
+      if (CY[j] > 0) ro += yp;
+      if (CY[j] < 0) ro += ym;
+      if (CZ[j] > 0) ro += zp;
+      if (CZ[j] < 0) ro += zm;
+      const uint32_t vx = CX[j] > 0 ? bxp : (CX[j] < 0 ? bxm : bx);
+      const T v = CachePolicy<S, 1>::nt_load(j) ? Raw<T>::template ld<CPOL_NT>(plane_rsrc(L, j, ES), vx, ro * ES)
+                                                 : Raw<T>::template ld<0>(plane_rsrc(L, j, ES), vx, ro * ES);
+      d[OPP[j]] = C::dec(v);
+    }
+  }
+  collide(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
+  if (P == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+      Raw<T>::template st<CPOL_NT>(plane_rsrc(L, OPP[i], ES), bx, C::enc(d[i]), r0 * ES);
+  } else {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      uint32_t ro = r0;
+      if (CY[j] > 0) ro += yp;
+      if (CY[j] < 0) ro += ym;
+      if (CZ[j] > 0) ro += zp;
+      if (CZ[j] < 0) ro += zm;
+      const uint32_t vx = CX[j] > 0 ? bxp : (CX[j] < 0 ? bxm : bx);
+      if (CachePolicy<S, 1>::nt_store(j)) Raw<T>::template st<CPOL_NT>(plane_rsrc(L, j, ES), vx, C::enc(d[j]), ro * ES);
+      else Raw<T>::template st<0>(plane_rsrc(L, j, ES), vx, C::enc(d[j]), ro * ES);
+    }
   }
 }
 

@@ -33,8 +33,24 @@ class LbParams(ctypes.Structure):
 
 
 class LbSchedule(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32), ("graph_chunk", ctypes.c_int32)]
+    _fields_ = [("block", ctypes.c_int32), ("order", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
+                ("xcd_remap", ctypes.c_int32 * 2), ("tiling", ctypes.c_int32 * 2)]
+
+
+def _sched_dict(s):
+    return {"block": s.block, "order": s.order, "graph_chunk": s.graph_chunk,
+            "xcd_remap": list(s.xcd_remap), "tiling": list(s.tiling)}
+
+
+def _pair(v):
+    """An int (both parities) or an (even, odd) pair."""
+    if isinstance(v, (list, tuple)):
+        return (ctypes.c_int32 * 2)(int(v[0]), int(v[1]))
+    return (ctypes.c_int32 * 2)(int(v), int(v))
+
+
+def _make_schedule(block, order, xcd_remap, graph_chunk, tiling):
+    return LbSchedule(int(block), int(order), int(graph_chunk), _pair(xcd_remap), _pair(tiling))
 
 
 # (name, restype, argtypes) of every entry point in include/lbf.h
@@ -198,10 +214,12 @@ class Lattice(_Gathers):
     def schedule(self):
         s = LbSchedule()
         _check(lib().lb_get_schedule(self._ctx, ctypes.byref(s)), "lb_get_schedule")
-        return {"block": s.block, "order": s.order, "xcd_remap": s.xcd_remap, "graph_chunk": s.graph_chunk}
+        return _sched_dict(s)
 
-    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16):
-        s = LbSchedule(block, order, xcd_remap, graph_chunk)
+    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0):
+        """xcd_remap and tiling: an int for both step parities or an
+        (even, odd) pair."""
+        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling)
         _check(lib().lb_set_schedule(self._ctx, ctypes.byref(s)), "lb_set_schedule")
 
     def autotune(self, steps=10):
@@ -292,10 +310,12 @@ class Ensemble:
     def schedule(self):
         s = LbSchedule()
         _check(lib().lb_get_schedule(self._ctx, ctypes.byref(s)), "lb_get_schedule")
-        return {"block": s.block, "order": s.order, "xcd_remap": s.xcd_remap, "graph_chunk": s.graph_chunk}
+        return _sched_dict(s)
 
-    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16):
-        s = LbSchedule(block, order, xcd_remap, graph_chunk)
+    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0):
+        """xcd_remap and tiling: an int for both step parities or an
+        (even, odd) pair."""
+        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling)
         _check(lib().lb_set_schedule(self._ctx, ctypes.byref(s)), "lb_set_schedule")
 
     def autotune(self, steps=10):

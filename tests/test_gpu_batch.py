@@ -48,7 +48,9 @@ def test_batch_equals_standalone(storage):
     want = standalone_states(REPS, storage, steps)
     for sched in [dict(block=256, order=0, xcd_remap=1, graph_chunk=16),
                   dict(block=64, order=1, xcd_remap=0, graph_chunk=4),
-                  dict(block=512, order=2, xcd_remap=1, graph_chunk=2)]:
+                  dict(block=512, order=2, xcd_remap=1, graph_chunk=2),
+                  dict(block=256, order=1, xcd_remap=0, graph_chunk=16, tiling=1),
+                  dict(block=128, order=0, xcd_remap=(1, 0), graph_chunk=8, tiling=(1, 0))]:
         ens = lbf.Ensemble(REPS, storage=storage, init="thermal")
         ens.set_schedule(**sched)
         ens.step(steps)
@@ -78,7 +80,7 @@ def test_autotune_leaves_state_and_counter_unchanged():
     ens.step(3)
     before = ens.pool.clone()
     rep = json.loads(ens.autotune(steps=4))
-    assert len(rep) == 4 * 3 * 2 and all(c["ms_per_step"] > 0 for c in rep)
+    assert len(rep) == 4 * 3 * 2 * 2 and all(c["even_ms"] > 0 and c["odd_ms"] > 0 for c in rep)
     assert ens.t == 3
     assert torch.equal(ens.pool, before)
     ens.step(10)

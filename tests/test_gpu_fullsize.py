@@ -58,12 +58,15 @@ def check_one_step(lat, cfg, pts, tol):
     assert worst < tol, worst
 
 
-@pytest.mark.parametrize("remap", [0, 1])
-def test_512_fp32_sampled_parity(remap):
+@pytest.mark.parametrize("remap,rows", [(None, None), (0, 0), (1, 1)])
+def test_512_fp32_sampled_parity(remap, rows):
+    """None: the library's default schedule (the one the benchmark starts its
+    tuning from)."""
     cfg = dict(workloads.LARGE)
-    say(f"512^3 fp32, xcd_remap={remap}")
+    say(f"512^3 fp32, xcd_remap={remap}, tiling={rows}")
     lat = lbf.Lattice(**cfg, storage="f32", init="thermal")
-    lat.set_schedule(block=256, order=0, xcd_remap=remap, graph_chunk=16)
+    if remap is not None:
+        lat.set_schedule(block=256, order=0, xcd_remap=remap, graph_chunk=16, tiling=rows)
     pts = sample_sites(512, 1500, seed=remap)
     check_one_step(lat, cfg, pts, 1e-5)      # even step (t = 0)
     lat.step(17)                             # one direct step and one 16-step graph replay: t = 18
@@ -79,8 +82,9 @@ def test_768_fp16_sampled_parity():
     populations exactly; the GPU's output differs by fp32 arithmetic plus
     one fp16 rounding of each stored d_i (relative 2^-11 of |d_i| <~ 1)."""
     cfg = dict(workloads.XLARGE)
-    say("768^3 fp16")
+    say("768^3 fp16, row tiling")
     lat = lbf.Lattice(**cfg, storage="f16", init="thermal")
+    lat.set_schedule(block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=1)
     pts = sample_sites(768, 800, seed=5)
     check_one_step(lat, cfg, pts, 2.0 ** -11)
     lat.step(2)

@@ -113,12 +113,32 @@ def test_graph_direct_and_schedules_bit_identical():
         ref.step(1)
     want = ref.state.clone()
     for sched in [dict(block=256, xcd_remap=1, graph_chunk=16), dict(block=64, xcd_remap=0, graph_chunk=4),
-                  dict(block=512, xcd_remap=1, graph_chunk=2), dict(block=128, xcd_remap=0, graph_chunk=36)]:
+                  dict(block=512, xcd_remap=1, graph_chunk=2), dict(block=128, xcd_remap=0, graph_chunk=36),
+                  dict(block=256, xcd_remap=1, graph_chunk=16, tiling=1),
+                  dict(block=64, xcd_remap=0, graph_chunk=6, tiling=1),
+                  dict(block=256, xcd_remap=(0, 1), graph_chunk=16, tiling=(1, 0))]:
         lat = lbf.Lattice(**cfg, init="thermal")
         lat.set_schedule(**sched)
         lat.step(37)
         assert torch.equal(lat.state, want), sched
         lat.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("dims", [(1, 1, 1), (3, 2, 5), (17, 13, 11), (64, 3, 2), (512, 2, 3)])
+def test_row_tiling_bit_identical(storage, dims):
+    """The row tiling (workgroups within one x-row, uniform y/z offsets)
+    gives the same bits as the flat tiling."""
+    nx, ny, nz = dims
+    cfg = dict(nx=nx, ny=ny, nz=nz, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.7,
+               gamma_odd=0.1, gamma_even=-0.2, seed=3)
+    a = lbf.Lattice(**cfg, storage=storage, init="thermal")
+    a.set_schedule(block=256, tiling=0)
+    a.step(9)
+    b = lbf.Lattice(**cfg, storage=storage, init="thermal")
+    b.set_schedule(block=256, tiling=1)
+    b.step(9)
+    assert torch.equal(a.state, b.state)
 
 
 def test_checkpoint_resume_bit_identical():
