@@ -190,8 +190,10 @@ typedef struct {
   int32_t order;        /* tile order: 0 replica order, 1 largest replica      */
                         /* first, 2 smallest replica first                     */
   int32_t graph_chunk;  /* steps per graph replay (>= 2, even)                 */
-  int32_t xcd_remap[2]; /* per step parity [even, odd]: 1 gives each XCD a     */
-                        /* contiguous range of tiles                           */
+  int32_t xcd_remap[2]; /* per step parity [even, odd]: which XCD takes which  */
+                        /* tile (workgroup i runs on XCD i % 8): 0 tile i;     */
+                        /* 1 each XCD one contiguous eighth of the tiles;      */
+                        /* g in 2..64 each XCD g consecutive tiles at a time   */
   int32_t tiling[2];    /* per step parity: 0 each workgroup takes `block`     */
                         /* consecutive sites; 1 each workgroup takes one       */
                         /* `block`-long segment of one x-row, so y/z offsets   */
@@ -204,7 +206,7 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
 
 /* Time every candidate schedule on a scratch copy of the state (the state
  * and step count of ctx are unchanged): for each block size and tile order,
- * every (xcd_remap, tiling) pair is timed on even and on odd steps
+ * every (xcd_remap in {0, 1, 2, 4, 8}, tiling) pair is timed on even and on odd steps
  * separately (`steps` >= 2 launches of each parity), and the fastest pair is
  * kept per parity.  Applies the best schedule and writes a JSON report (one
  * object per candidate with its mean even and odd step times) into report

@@ -420,11 +420,12 @@ int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity
 
 // Default schedule, from measurements on MI355X (512^3 box): fp32 runs the
 // even step row-tiled and the odd step flat, both without XCD remapping; the
-// 16-bit forms run both parities row-tiled with remapping.  lb_autotune
-// refines it for a given workload.
+// 16-bit forms run the even step flat and the odd step row-tiled, both with
+// XCD groups of 8 consecutive tiles.  lb_autotune refines it for a given
+// workload.
 int default_schedule(lb_ctx* c) {
   if (c->storage == LB_F32) c->sched = lb_schedule{256, 0, 16, {0, 0}, {1, 0}};
-  else c->sched = lb_schedule{256, 0, 16, {1, 1}, {1, 1}};
+  else c->sched = lb_schedule{256, 0, 16, {8, 8}, {0, 1}};
   if (c->wide) c->sched.tiling[0] = c->sched.tiling[1] = 0;
   return upload_schedule(c);
 }
@@ -690,7 +691,8 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s) {
     return fail(LB_EINVAL, "block must be 64, 128, 256 or 512");
   if (s->order < 0 || s->order > 2) return fail(LB_EINVAL, "order must be 0, 1 or 2");
   for (int q = 0; q < 2; ++q) {
-    if (s->xcd_remap[q] != 0 && s->xcd_remap[q] != 1) return fail(LB_EINVAL, "xcd_remap entries must be 0 or 1");
+    if (s->xcd_remap[q] < 0 || s->xcd_remap[q] > 64)
+      return fail(LB_EINVAL, "xcd_remap entries must be 0 (off), 1 (contiguous) or a group size 2..64");
     if (s->tiling[q] != 0 && s->tiling[q] != 1) return fail(LB_EINVAL, "tiling entries must be 0 or 1");
     if (s->tiling[q] && ctx->wide) return fail(LB_EUNSUPPORTED, "the row tiling needs planes below 4 GiB");
   }
@@ -742,8 +744,10 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
     for (int ord = 0; ord < norders && rc == LB_OK; ++ord) {
       double par_best[2] = {1e300, 1e300};
       int par_remap[2] = {0, 0}, par_tiling[2] = {0, 0};
-      for (int remap = 0; remap < 2 && rc == LB_OK; ++remap)
+      const int remaps[] = {0, 1, 2, 4, 8};
+      for (int ri = 0; ri < 5 && rc == LB_OK; ++ri)
         for (int til = 0; til < ntiling && rc == LB_OK; ++til) {
+          const int remap = remaps[ri];
           ctx->sched = lb_schedule{blocks[bi], ord, saved.graph_chunk, {remap, remap}, {til, til}};
           if ((rc = upload_schedule(ctx))) break;
           if ((rc = direct_steps(ctx, 2))) break;  // warm-up

@@ -316,11 +316,24 @@ __device__ __forceinline__ void collide(const LatDesc& L, float d[Q], uint32_t s
 }
 
 // ---------------------------------------------------------------- tile lookup
-// Blocks are dealt to the eight XCDs round-robin; the remap hands each XCD a
-// contiguous range of logical tiles so neighbouring tiles share an L2.
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t i, uint32_t G) {
-  const uint32_t q = G >> 3, r = G & 7u, x = i & 7u, k = i >> 3;
-  return x * q + (x < r ? x : r) + k;
+// Blocks are dealt to the eight XCDs round-robin (block i runs on XCD i % 8),
+// and each XCD has its own L2.  The remap decides which logical tile block i
+// takes: mode 0 keeps tile i (consecutive tiles on different XCDs); mode 1
+// gives each XCD one contiguous eighth of the tiles; mode g >= 2 gives each
+// XCD g consecutive tiles at a time, so tiles that share cache lines (the two
+// halves of an x-row, say) share an L2 while the XCDs still walk the lattice
+// together.  Every mode is a bijection on [0, G).
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t i, uint32_t G, uint32_t mode) {
+  if (mode == 0) return i;
+  if (mode == 1) {
+    const uint32_t q = G >> 3, r = G & 7u, x = i & 7u, k = i >> 3;
+    return x * q + (x < r ? x : r) + k;
+  }
+  const uint32_t S = 8u * mode;                 // one super-group: g tiles on each XCD
+  const uint32_t full = (G / S) * S;
+  if (i >= full) return i;                      // ragged tail keeps its order
+  const uint32_t base = i - i % S, r = i % S;
+  return base + (r & 7u) * mode + (r >> 3);
 }
 
 // Lattice of logical block b: blk[l] <= b < blk[l + 1] (uniform search).
@@ -342,7 +355,7 @@ k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint3
        uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   using C = Codec<S>;
-  const uint32_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, remap);
   uint32_t l = 0;
   if (nlat > 1) l = find_lattice(blk, nlat, b);
   const LatDesc& L = lats[l];
@@ -379,7 +392,7 @@ k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
   using C = Codec<S>;
   using T = typename C::T;
   constexpr uint32_t ES = sizeof(T);
-  const uint32_t b = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, remap);
   uint32_t l = 0;
   if (nlat > 1) l = find_lattice(blk, nlat, b);
   const LatDesc& L = lats[l];

@@ -80,7 +80,7 @@ def test_autotune_leaves_state_and_counter_unchanged():
     ens.step(3)
     before = ens.pool.clone()
     rep = json.loads(ens.autotune(steps=4))
-    assert len(rep) == 4 * 3 * 2 * 2 and all(c["even_ms"] > 0 and c["odd_ms"] > 0 for c in rep)
+    assert len(rep) == 4 * 3 * 5 * 2 and all(c["even_ms"] > 0 and c["odd_ms"] > 0 for c in rep)
     assert ens.t == 3
     assert torch.equal(ens.pool, before)
     ens.step(10)
