@@ -1,17 +1,17 @@
 /*
- * lbora.c -- plain FP64 CPU oracle for the fluctuating D3Q19 lattice
- * Boltzmann update of Duenweg, Schiller & Ladd, "Statistical mechanics of
- * the fluctuating lattice Boltzmann equation" (arXiv:0707.1581).
+ * lbora.c -- plain FP64 CPU oracle for the fluctuating lattice Boltzmann
+ * update (D3Q19 and D2Q9) of Duenweg, Schiller & Ladd, "Statistical
+ * mechanics of the fluctuating lattice Boltzmann equation" (arXiv:0707.1581).
  *
  * TEST INFRASTRUCTURE, NOT PRODUCT CODE.  Only the test suite, the smoke
  * check and the CPU-baseline leg of the benchmark may load this library.
  * It shares no code, header, table or constant with the GPU library: its
- * tables are built here from the velocity set and the polynomials of the
- * paper's Table II, its Philox generator is written here from the published
+ * tables are built here from the velocity sets and the polynomials of the
+ * paper's Tables I and II, its Philox generator is written here from the published
  * definition, and every step is the plain definition:
  *
- *   - moments m_k = sum_i e_ki n_i with dense 19x19 loops (Eq. modes with
- *     the unscaled Table II basis, Sec. III),
+ *   - moments m_k = sum_i e_ki n_i with dense q x q loops (Eq. modes with
+ *     the unscaled basis of Table II or Table I, Sec. III),
  *   - equilibrium populations by Eq. (derived_equil_distrib) with
  *     sigma_2 = c_s^2 = 1/3, projected onto the same basis,
  *   - per-mode update m* = m^eq + gamma_k (m - m^eq) + sqrt(mu rho w_k
@@ -37,26 +37,55 @@
 #include <omp.h>
 #endif
 
-#define Q 19
+#define QMAX 19
 
 /* ------------------------------------------------------------------ */
-/* Velocity set and weights (Sec. II: D3Q19, a^0 = 1/3, a^1 = 1/18,     */
-/* a^sqrt2 = 1/36).  Order: rest; +x -x +y -y +z -z; then the twelve    */
-/* diagonals in opposite pairs.  The opposite of i is i+1 (odd i) or    */
-/* i-1 (even i > 0).                                                    */
+/* Lattices.  Two velocity sets of the paper (Sec. III): D3Q19 with the   */
+/* basis of Table II and D2Q9 with the basis of Table I.  Both have three */
+/* speeds (0, 1, sqrt 2) and c_s^2 = 1/3.  Velocity order: rest; the axis */
+/* directions as (+x, -x, +y, -y[, +z, -z]); then the diagonals in        */
+/* opposite pairs.  The opposite of i is i+1 (odd i) or i-1 (even i > 0). */
 /* ------------------------------------------------------------------ */
-static const int VEL[Q][3] = {
+enum { LAT_D3Q19 = 0, LAT_D2Q9 = 1, NLAT = 2 };
+
+/* Mode classes (Sec. IV: each mode relaxes at its own rate, subject to   */
+/* symmetry): conserved (mass, momentum), bulk stress, shear stress, odd  */
+/* (third-order) and even (fourth-order) kinetic modes.                   */
+enum { MODE_CONSERVED = 0, MODE_BULK, MODE_SHEAR, MODE_ODD, MODE_EVEN };
+
+typedef struct {
+  int q, d;
+  int vel[QMAX][3];
+  double a[QMAX];        /* a^{c_i}                    */
+  double e[QMAX][QMAX];  /* e_ki, [k][i]               */
+  double w[QMAX];        /* w_k = sum_i a_i e_ki^2     */
+  int cls[QMAX];         /* mode class of k            */
+} lattice;
+
+static const int VEL_D3Q19[19][3] = {
     {0, 0, 0},
     {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
     {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
     {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
     {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
 
-static double weight_of(const int c[3]) {
+static const int VEL_D2Q9[9][3] = {
+    {0, 0, 0},
+    {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0},
+    {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}};
+
+/* Weights by speed.  D3Q19: a^0 = 1/3, a^1 = 1/18, a^sqrt2 = 1/36 (Sec. II).
+ * D2Q9: the paper gives no numbers but states that normalisation and the
+ * isotropy conditions sigma_2 = c_s^2, sigma_4 = sigma_2^2, kappa_4 = 0
+ * (Eqs. equilcond2-4) fix the weights of a three-speed model.  With one
+ * rest, four axis and four diagonal velocities: sum_i a_i c_ix^4 =
+ * 2 a1 + 4 a2 must equal 3 sigma_4 = 3 * 4 a2 (kappa_4 = 0), so a1 = 4 a2;
+ * sigma_4 = 4 a2 = (2 a1 + 4 a2)^2 = (12 a2)^2 gives a2 = 1/36, a1 = 1/9,
+ * and a0 = 1 - 4 a1 - 4 a2 = 4/9, with c_s^2 = 2 a1 + 4 a2 = 1/3. */
+static double weight_of(int lat, const int c[3]) {
   int c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
-  if (c2 == 0) return 1.0 / 3.0;
-  if (c2 == 1) return 1.0 / 18.0;
-  return 1.0 / 36.0;
+  if (lat == LAT_D3Q19) return c2 == 0 ? 1.0 / 3.0 : (c2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+  return c2 == 0 ? 4.0 / 9.0 : (c2 == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
 }
 
 /* Table II: the D3Q19 basis polynomial e_k(c), with c in lattice units. */
@@ -87,36 +116,87 @@ static double table2_poly(int k, const int c[3]) {
   return 0.0;
 }
 
-static double A[Q];      /* a_i                        */
-static double E[Q][Q];   /* e_ki, [k][i]               */
-static double W[Q];      /* w_k = sum_i a_i e_ki^2     */
+/* Table I: the D2Q9 basis polynomial e_k(c). */
+static double table1_poly(int k, const int c[3]) {
+  double cx = c[0], cy = c[1];
+  double c2 = cx * cx + cy * cy;
+  switch (k) {
+    case 0: return 1.0;
+    case 1: return cx;
+    case 2: return cy;
+    case 3: return 3.0 * c2 - 2.0;
+    case 4: return 2.0 * cx * cx - c2;
+    case 5: return cx * cy;
+    case 6: return (3.0 * c2 - 4.0) * cx;
+    case 7: return (3.0 * c2 - 4.0) * cy;
+    case 8: return 9.0 * c2 * c2 - 15.0 * c2 + 2.0;
+  }
+  return 0.0;
+}
+
+/* Mode classes in table order: D3Q19 k = 0..3 conserved, 4 bulk, 5..9
+ * shear, 10..15 odd, 16..18 even; D2Q9 k = 0..2 conserved, 3 bulk, 4..5
+ * shear, 6..7 odd, 8 even (Sec. III: d + 1 conserved modes, one bulk mode,
+ * d(d+1)/2 - 1 shear modes, then the kinetic modes). */
+static int mode_class(int lat, int k) {
+  if (lat == LAT_D3Q19) {
+    if (k <= 3) return MODE_CONSERVED;
+    if (k == 4) return MODE_BULK;
+    if (k <= 9) return MODE_SHEAR;
+    return k <= 15 ? MODE_ODD : MODE_EVEN;
+  }
+  if (k <= 2) return MODE_CONSERVED;
+  if (k == 3) return MODE_BULK;
+  if (k <= 5) return MODE_SHEAR;
+  return k <= 7 ? MODE_ODD : MODE_EVEN;
+}
+
+static lattice LATS[NLAT];
 static int tables_ready = 0;
 
 static void build_tables(void) {
   if (tables_ready) return;
-  for (int i = 0; i < Q; ++i) A[i] = weight_of(VEL[i]);
-  for (int k = 0; k < Q; ++k) {
-    double s = 0.0;
-    for (int i = 0; i < Q; ++i) {
-      E[k][i] = table2_poly(k, VEL[i]);
-      s += A[i] * E[k][i] * E[k][i];
+  for (int l = 0; l < NLAT; ++l) {
+    lattice* L = &LATS[l];
+    L->q = (l == LAT_D3Q19) ? 19 : 9;
+    L->d = (l == LAT_D3Q19) ? 3 : 2;
+    for (int i = 0; i < L->q; ++i) {
+      for (int c = 0; c < 3; ++c) L->vel[i][c] = (l == LAT_D3Q19) ? VEL_D3Q19[i][c] : VEL_D2Q9[i][c];
+      L->a[i] = weight_of(l, L->vel[i]);
     }
-    W[k] = s; /* the "length" of basis vector k, Sec. III */
+    for (int k = 0; k < L->q; ++k) {
+      double s = 0.0;
+      for (int i = 0; i < L->q; ++i) {
+        L->e[k][i] = (l == LAT_D3Q19) ? table2_poly(k, L->vel[i]) : table1_poly(k, L->vel[i]);
+        s += L->a[i] * L->e[k][i] * L->e[k][i];
+      }
+      L->w[k] = s; /* the "length" of basis vector k, Sec. III */
+      L->cls[k] = mode_class(l, k);
+    }
   }
   tables_ready = 1;
 }
 
-/* Exported for the table pins: c[19][3], a[19], e[19][19] ([k][i]), w[19]. */
-void ora_tables(int32_t* c, double* a, double* e, double* w) {
+static const lattice* lattice_of(int32_t lat) {
   build_tables();
-  for (int i = 0; i < Q; ++i) {
-    for (int d = 0; d < 3; ++d) c[3 * i + d] = VEL[i][d];
-    a[i] = A[i];
+  return (lat >= 0 && lat < NLAT) ? &LATS[lat] : NULL;
+}
+
+/* Exported for the table pins: returns q and fills c[q][3], a[q], e[q][q]
+ * ([k][i]) and w[q]; -1 for an unknown lattice. */
+int32_t ora_tables(int32_t lat, int32_t* c, double* a, double* e, double* w) {
+  const lattice* L = lattice_of(lat);
+  if (!L) return -1;
+  const int q = L->q;
+  for (int i = 0; i < q; ++i) {
+    for (int d = 0; d < 3; ++d) c[3 * i + d] = L->vel[i][d];
+    a[i] = L->a[i];
   }
-  for (int k = 0; k < Q; ++k) {
-    w[k] = W[k];
-    for (int i = 0; i < Q; ++i) e[Q * k + i] = E[k][i];
+  for (int k = 0; k < q; ++k) {
+    w[k] = L->w[k];
+    for (int i = 0; i < q; ++i) e[q * k + i] = L->e[k][i];
   }
+  return q;
 }
 
 /* ------------------------------------------------------------------ */
@@ -207,10 +287,9 @@ void ora_normals(uint64_t seed, uint32_t site, uint64_t t, uint32_t stream,
 }
 
 /* ------------------------------------------------------------------ */
-/* Parameters and the per-mode rates (Sec. IV, "each mode ... its own   */
-/* gamma_k"): k <= 3 conserved (gamma = 1); k = 4 bulk; k = 5..9 shear;  */
-/* k = 10..15 odd (third-order) kinetic modes; k = 16..18 even           */
-/* (fourth-order) kinetic modes.                                         */
+/* Parameters and the per-mode rates (Sec. IV: every non-conserved mode  */
+/* relaxes at a rate of its own, equal within a symmetry class): bulk,   */
+/* shear, odd and even kinetic rates.                                    */
 /* ------------------------------------------------------------------ */
 typedef struct {
   int64_t nx, ny, nz;
@@ -219,81 +298,104 @@ typedef struct {
   double gamma_bulk, gamma_shear, gamma_odd, gamma_even;
   uint64_t seed;
   int32_t thermal_modes; /* 0: all non-conserved modes; 1: stress modes only */
-  int32_t reserved;
+  int32_t lattice;       /* LAT_D3Q19 or LAT_D2Q9 (then nz = 1)             */
 } ora_params;
 
-static double mode_gamma(const ora_params* p, int k) {
-  if (k <= 3) return 1.0;
-  if (k == 4) return p->gamma_bulk;
-  if (k <= 9) return p->gamma_shear;
-  if (k <= 15) return p->gamma_odd;
-  return p->gamma_even;
+static double mode_gamma(const ora_params* p, int cls) {
+  switch (cls) {
+    case MODE_CONSERVED: return 1.0;
+    case MODE_BULK: return p->gamma_bulk;
+    case MODE_SHEAR: return p->gamma_shear;
+    case MODE_ODD: return p->gamma_odd;
+    default: return p->gamma_even;
+  }
 }
 
-static int mode_thermalised(const ora_params* p, int k) {
-  if (k <= 3) return 0;
-  if (k <= 9) return 1;
+static int mode_thermalised(const ora_params* p, int cls) {
+  if (cls == MODE_CONSERVED) return 0;
+  if (cls == MODE_BULK || cls == MODE_SHEAR) return 1;
   return p->thermal_modes == 0;
 }
 
-/* Eq. (derived_equil_distrib) with sigma_2 = c_s^2 = 1/3. */
-void ora_equilibrium(double rho, const double u[3], double* neq) {
-  build_tables();
-  const double cs2 = 1.0 / 3.0;
-  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  for (int i = 0; i < Q; ++i) {
-    double uc = u[0] * VEL[i][0] + u[1] * VEL[i][1] + u[2] * VEL[i][2];
-    neq[i] = rho * A[i] * (1.0 + uc / cs2 + uc * uc / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
-  }
+/* A usable parameter set: known lattice, positive sizes, nz = 1 in 2D. */
+static const lattice* params_lattice(const ora_params* p) {
+  const lattice* L = lattice_of(p->lattice);
+  if (!L || p->nx < 1 || p->ny < 1 || p->nz < 1) return NULL;
+  if (L->d == 2 && p->nz != 1) return NULL;
+  return L;
 }
 
-/* One collision at one site, in place.  Returns 0, or -1 if rho <= 0 or
- * rho is not finite (the Gaussian model needs positive local mass). */
+/* Eq. (derived_equil_distrib) with sigma_2 = c_s^2 = 1/3; u has three
+ * components, of which a 2D lattice uses the first two. */
+int ora_equilibrium(int32_t lat, double rho, const double u[3], double* neq) {
+  const lattice* L = lattice_of(lat);
+  if (!L) return -1;
+  const double cs2 = 1.0 / 3.0;
+  double uu = 0.0;
+  for (int c = 0; c < L->d; ++c) uu += u[c] * u[c];
+  for (int i = 0; i < L->q; ++i) {
+    double uc = 0.0;
+    for (int c = 0; c < L->d; ++c) uc += u[c] * L->vel[i][c];
+    neq[i] = rho * L->a[i] * (1.0 + uc / cs2 + uc * uc / (2.0 * cs2 * cs2) - uu / (2.0 * cs2));
+  }
+  return 0;
+}
+
+/* One collision at one site, in place.  Returns 0, -1 if rho <= 0 or rho
+ * is not finite (the Gaussian model needs positive local mass), -2 for
+ * unusable parameters.
+ *
+ * Noise: the q - d - 1 non-conserved modes take, in table order, the
+ * normals of stream 0 of (seed, site, t): normal s goes to mode d + 1 + s. */
 int ora_collide_site(const ora_params* p, double* n, uint32_t site, uint64_t t) {
-  build_tables();
+  const lattice* L = params_lattice(p);
+  if (!L) return -2;
+  const int q = L->q, d = L->d;
   double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < q; ++i) {
     rho += n[i];
-    for (int d = 0; d < 3; ++d) j[d] += n[i] * VEL[i][d];
+    for (int c = 0; c < d; ++c) j[c] += n[i] * L->vel[i][c];
   }
   if (!(rho > 0.0) || !isfinite(rho)) return -1;
   double u[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
-  double neq[Q];
-  ora_equilibrium(rho, u, neq);
+  double neq[QMAX];
+  ora_equilibrium(p->lattice, rho, u, neq);
 
-  double m[Q], meq[Q], ms[Q];
-  for (int k = 0; k < Q; ++k) {
+  double m[QMAX], meq[QMAX], ms[QMAX];
+  for (int k = 0; k < q; ++k) {
     double s = 0.0, se = 0.0;
-    for (int i = 0; i < Q; ++i) {
-      s += E[k][i] * n[i];
-      se += E[k][i] * neq[i];
+    for (int i = 0; i < q; ++i) {
+      s += L->e[k][i] * n[i];
+      se += L->e[k][i] * neq[i];
     }
     m[k] = s;
     meq[k] = se;
   }
 
-  double mu = 3.0 * p->kT; /* mu = kT / c_s^2 in lattice units */
-  double r[16] = {0};
-  if (p->kT > 0.0) ora_normals(p->seed, site, t, 0, 15, r);
+  const double mu = 3.0 * p->kT; /* mu = kT / c_s^2 in lattice units */
+  const int first = d + 1;      /* first non-conserved mode */
+  double r[QMAX + 1] = {0};
+  if (p->kT > 0.0) ora_normals(p->seed, site, t, 0, q - first, r);
 
-  for (int k = 0; k < Q; ++k) {
-    if (k <= 3) {
+  for (int k = 0; k < q; ++k) {
+    const int cls = L->cls[k];
+    if (cls == MODE_CONSERVED) {
       ms[k] = m[k];
       continue;
     }
-    double g = mode_gamma(p, k);
+    double g = mode_gamma(p, cls);
     double mk = meq[k] + g * (m[k] - meq[k]);
-    if (p->kT > 0.0 && mode_thermalised(p, k)) {
+    if (p->kT > 0.0 && mode_thermalised(p, cls)) {
       /* noise on mode k: sqrt(mu rho w_k (1 - gamma_k^2)) r, local rho */
-      mk += sqrt(mu * rho * W[k] * (1.0 - g * g)) * r[k - 4];
+      mk += sqrt(mu * rho * L->w[k] * (1.0 - g * g)) * r[k - first];
     }
     ms[k] = mk;
   }
 
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 0; i < q; ++i) {
     double s = 0.0;
-    for (int k = 0; k < Q; ++k) s += E[k][i] * ms[k] / W[k];
-    n[i] = A[i] * s;
+    for (int k = 0; k < q; ++k) s += L->e[k][i] * ms[k] / L->w[k];
+    n[i] = L->a[i] * s;
   }
   return 0;
 }
@@ -309,9 +411,12 @@ static int64_t wrap(int64_t v, int64_t L) {
 
 /* One step: collide every site of n_in with noise keyed on t, push the
  * post-collision populations along c_i into n_out.  Returns the number of
- * sites with rho <= 0 (those sites stream their pre-collision values). */
+ * sites with rho <= 0 (those sites stream their pre-collision values), or
+ * -1 for unusable parameters. */
 int64_t ora_step(const ora_params* p, const double* n_in, double* n_out, uint64_t t) {
-  build_tables();
+  const lattice* L = params_lattice(p);
+  if (!L) return -1;
+  const int q = L->q;
   const int64_t nx = p->nx, ny = p->ny, nz = p->nz;
   const int64_t N = nx * ny * nz;
   int64_t bad = 0;
@@ -320,13 +425,13 @@ int64_t ora_step(const ora_params* p, const double* n_in, double* n_out, uint64_
     for (int64_t y = 0; y < ny; ++y) {
       for (int64_t x = 0; x < nx; ++x) {
         int64_t s = x + nx * (y + ny * z);
-        double n[Q];
-        for (int i = 0; i < Q; ++i) n[i] = n_in[i * N + s];
+        double n[QMAX];
+        for (int i = 0; i < q; ++i) n[i] = n_in[i * N + s];
         if (ora_collide_site(p, n, (uint32_t)s, t) != 0) bad += 1;
-        for (int i = 0; i < Q; ++i) {
-          int64_t xd = wrap(x + VEL[i][0], nx);
-          int64_t yd = wrap(y + VEL[i][1], ny);
-          int64_t zd = wrap(z + VEL[i][2], nz);
+        for (int i = 0; i < q; ++i) {
+          int64_t xd = wrap(x + L->vel[i][0], nx);
+          int64_t yd = wrap(y + L->vel[i][1], ny);
+          int64_t zd = wrap(z + L->vel[i][2], nz);
           n_out[i * N + xd + nx * (yd + ny * zd)] = n[i];
         }
       }
@@ -338,11 +443,13 @@ int64_t ora_step(const ora_params* p, const double* n_in, double* n_out, uint64_
 /* nsteps steps starting at step count t0; n holds the state on entry and
  * on exit, tmp is a second buffer of the same size. */
 int64_t ora_run(const ora_params* p, double* n, double* tmp, uint64_t t0, int64_t nsteps) {
+  const lattice* L = params_lattice(p);
+  if (!L) return -1;
   const int64_t N = p->nx * p->ny * p->nz;
   int64_t bad = 0;
   for (int64_t s = 0; s < nsteps; ++s) {
     bad += ora_step(p, n, tmp, t0 + (uint64_t)s);
-    memcpy(n, tmp, sizeof(double) * (size_t)(Q * N));
+    memcpy(n, tmp, sizeof(double) * (size_t)(L->q * N));
   }
   return bad;
 }
@@ -352,63 +459,73 @@ int64_t ora_run(const ora_params* p, double* n, double* tmp, uint64_t t0, int64_
  * n_i = a_i rho0 + sqrt(mu rho0 a_i) sum_k ehat_ki z_k with
  * ehat_ki = sqrt(a_i / w_k) e_ki (Eqs. xdef, x_s, evectors_orthonormal);
  * normals from stream 1, normal k -> mode k.  kind 2: n_i = n_i^eq(rho, u)
- * from fields[4][N] = (rho, ux, uy, uz). */
+ * from fields[1 + d][N] = (rho, ux, uy[, uz]). */
 int ora_init(const ora_params* p, int32_t kind, const double* fields, double* n) {
-  build_tables();
+  const lattice* L = params_lattice(p);
+  if (!L) return -1;
+  const int q = L->q, d = L->d;
   const int64_t N = p->nx * p->ny * p->nz;
   double mu = 3.0 * p->kT;
   if (kind == 2 && fields == NULL) return -1;
   if (kind < 0 || kind > 2) return -1;
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; ++s) {
-    double v[Q];
+    double v[QMAX];
     if (kind == 0) {
-      for (int i = 0; i < Q; ++i) v[i] = A[i] * p->rho0;
+      for (int i = 0; i < q; ++i) v[i] = L->a[i] * p->rho0;
     } else if (kind == 1) {
-      double z[Q + 1];
-      ora_normals(p->seed, (uint32_t)s, 0, 1, Q, z);
-      for (int i = 0; i < Q; ++i) {
+      double z[QMAX + 1];
+      ora_normals(p->seed, (uint32_t)s, 0, 1, q, z);
+      for (int i = 0; i < q; ++i) {
         double x = 0.0;
-        for (int k = 0; k < Q; ++k) x += sqrt(A[i] / W[k]) * E[k][i] * z[k];
-        v[i] = A[i] * p->rho0 + sqrt(mu * p->rho0 * A[i]) * x;
+        for (int k = 0; k < q; ++k) x += sqrt(L->a[i] / L->w[k]) * L->e[k][i] * z[k];
+        v[i] = L->a[i] * p->rho0 + sqrt(mu * p->rho0 * L->a[i]) * x;
       }
     } else {
-      double u[3] = {fields[N + s], fields[2 * N + s], fields[3 * N + s]};
-      ora_equilibrium(fields[s], u, v);
+      double u[3] = {0.0, 0.0, 0.0};
+      for (int c = 0; c < d; ++c) u[c] = fields[(c + 1) * N + s];
+      ora_equilibrium(p->lattice, fields[s], u, v);
     }
-    for (int i = 0; i < Q; ++i) n[i * N + s] = v[i];
+    for (int i = 0; i < q; ++i) n[i * N + s] = v[i];
   }
   return 0;
 }
 
-/* rho, jx, jy, jz per site (Eqs. defrho, defj): out[4][N]. */
-void ora_moments(const ora_params* p, const double* n, double* out) {
+/* rho and j per site (Eqs. defrho, defj): out[1 + d][N]. */
+int ora_moments(const ora_params* p, const double* n, double* out) {
+  const lattice* L = params_lattice(p);
+  if (!L) return -1;
+  const int q = L->q, d = L->d;
   const int64_t N = p->nx * p->ny * p->nz;
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; ++s) {
     double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 0; i < q; ++i) {
       rho += n[i * N + s];
-      for (int d = 0; d < 3; ++d) j[d] += n[i * N + s] * VEL[i][d];
+      for (int c = 0; c < d; ++c) j[c] += n[i * N + s] * L->vel[i][c];
     }
     out[s] = rho;
-    for (int d = 0; d < 3; ++d) out[(d + 1) * N + s] = j[d];
+    for (int c = 0; c < d; ++c) out[(c + 1) * N + s] = j[c];
   }
+  return 0;
 }
 
 /* Unscaled modes of the deviation from rest, m_k = sum_i e_ki (n_i - a_i rho0),
- * out[19][N] (k = 0 gives rho - rho0; for k >= 1 the rest part vanishes). */
-void ora_modes(const ora_params* p, const double* n, double* out) {
-  build_tables();
+ * out[q][N] (k = 0 gives rho - rho0; for k >= 1 the rest part vanishes). */
+int ora_modes(const ora_params* p, const double* n, double* out) {
+  const lattice* L = params_lattice(p);
+  if (!L) return -1;
+  const int q = L->q;
   const int64_t N = p->nx * p->ny * p->nz;
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < N; ++s) {
-    for (int k = 0; k < Q; ++k) {
+    for (int k = 0; k < q; ++k) {
       double acc = 0.0;
-      for (int i = 0; i < Q; ++i) acc += E[k][i] * (n[i * N + s] - A[i] * p->rho0);
+      for (int i = 0; i < q; ++i) acc += L->e[k][i] * (n[i * N + s] - L->a[i] * p->rho0);
       out[k * N + s] = acc;
     }
   }
+  return 0;
 }
 
 int32_t ora_num_threads(void) {

@@ -30,10 +30,11 @@ def load_weights():
     return out, cs2
 
 
-def load_table2():
-    """[(k, polynomial source, Fraction w_k)] from Table II."""
+def load_table2(name="table2_d3q19.txt"):
+    """[(k, polynomial source, Fraction w_k)] from Table II (or, with
+    name="table1_d2q9.txt", from Table I)."""
     rows = []
-    with open(os.path.join(GOLDEN, "table2_d3q19.txt")) as f:
+    with open(os.path.join(GOLDEN, name)) as f:
         for line in f:
             if line.startswith("#") or not line.strip():
                 continue
@@ -42,10 +43,10 @@ def load_table2():
     return rows
 
 
-def table2_matrix(c):
+def table2_matrix(c, name="table2_d3q19.txt"):
     """e[k, i] evaluated exactly (Fractions) from the Table II polynomials
-    for the velocity list c (19 x 3 integers)."""
-    rows = load_table2()
+    (or those of another fixture) for the velocity list c (q x 3 integers)."""
+    rows = load_table2(name)
     e = [[None] * len(c) for _ in rows]
     for k, poly, _ in rows:
         for i, (cx, cy, cz) in enumerate(c):
@@ -102,7 +103,7 @@ def chunks24_py(seed, site, t, stream, n):
 
 # ---------------------------------------------------------------- linear operator
 def one_step_operator(q_vec, gammas, c, a, e, w):
-    """19x19 linearised collide-and-push operator for a plane wave
+    """q x q linearised collide-and-push operator for a plane wave
     exp(i q.r): L = diag(exp(-i q.c_i)) * Minv diag(gamma) M with M = e
     (m = M n) and Minv[i, k] = a_i e_ki / w_k."""
     M = np.asarray(e, dtype=float)
@@ -112,34 +113,48 @@ def one_step_operator(q_vec, gammas, c, a, e, w):
     return phase[:, None] * C
 
 
-def mode_gammas(gb, gs, go, ge):
-    g = np.ones(19)
-    g[4] = gb
-    g[5:10] = gs
-    g[10:16] = go
-    g[16:19] = ge
+def mode_gammas(gb, gs, go, ge, q=19):
+    """Per-mode rates in table order: D3Q19 (q = 19) k = 4 bulk, 5..9 shear,
+    10..15 odd, 16..18 even; D2Q9 (q = 9) k = 3 bulk, 4..5 shear, 6..7 odd,
+    8 even; conserved modes 1."""
+    g = np.ones(q)
+    if q == 19:
+        g[4] = gb
+        g[5:10] = gs
+        g[10:16] = go
+        g[16:19] = ge
+    else:
+        g[3] = gb
+        g[4:6] = gs
+        g[6:8] = go
+        g[8] = ge
     return g
 
 
-def shear_eigenvalue(L, n, gammas, c, a, e, w):
-    """Eigenvalue of the transverse-momentum (j_x, wave vector along z)
-    mode: the eigenvector with the largest overlap with j_x."""
+def shear_eigenvalue(L, n, gammas, c, a, e, w, axis=2):
+    """Eigenvalue of the transverse-momentum (j_x, wave vector along z, or
+    along `axis`) mode: the eigenvector with the largest overlap with j_x."""
     q = 2 * np.pi * n / L
-    Lop = one_step_operator([0, 0, q], gammas, c, a, e, w)
+    qv = [0.0, 0.0, 0.0]
+    qv[axis] = q
+    Lop = one_step_operator(qv, gammas, c, a, e, w)
     vals, vecs = np.linalg.eig(Lop)
     jx = np.asarray(c, dtype=float)[:, 0]
     best = np.argmax(np.abs(jx @ vecs) / np.linalg.norm(vecs, axis=0))
     return vals[best]
 
 
-def sound_eigenvalue(L, n, gammas, c, a, e, w):
-    """Eigenvalue of the forward sound mode (wave vector along z): the
-    eigenvector with the largest density + j_z overlap, positive frequency."""
+def sound_eigenvalue(L, n, gammas, c, a, e, w, axis=2):
+    """Eigenvalue of the forward sound mode (wave vector along z, or along
+    `axis`): the eigenvector with the largest density + longitudinal
+    momentum overlap, positive frequency."""
     q = 2 * np.pi * n / L
-    Lop = one_step_operator([0, 0, q], gammas, c, a, e, w)
+    qv = [0.0, 0.0, 0.0]
+    qv[axis] = q
+    Lop = one_step_operator(qv, gammas, c, a, e, w)
     vals, vecs = np.linalg.eig(Lop)
-    cz = np.asarray(c, dtype=float)[:, 2]
-    ov = (np.abs(np.ones(19) @ vecs) + np.abs(cz @ vecs)) / np.linalg.norm(vecs, axis=0)
+    cz = np.asarray(c, dtype=float)[:, axis]
+    ov = (np.abs(np.ones(len(cz)) @ vecs) + np.abs(cz @ vecs)) / np.linalg.norm(vecs, axis=0)
     order = np.argsort(-ov)
     for idx in order[:4]:
         if np.angle(vals[idx]) < 0:  # exp(-i w) convention of the push
@@ -183,3 +198,76 @@ def neq_modes(modes, rho0):
     for k in range(4):
         out[k] = m[k] - m[k].mean()
     return out
+
+
+# ---------------------------------------------------------------- macroscopic random stress
+def box_random_stress(m_before, m_after, rho0, gammas, c, a, e, w):
+    """Box sum of the random stress R_ab that one collision adds (Sec. IV),
+    from the gathered modes ((q, ...) of n - a rho0) at t and at t + 1.
+
+    Streaming moves every population to another site but keeps the box total
+    of each direction, so the box sum of each mode after the step equals the
+    box sum of the post-collision modes.  Subtracting the deterministic part
+    m^eq + gamma_k (m - m^eq) of the modes at t leaves sum_r R_k(r) for the
+    non-conserved modes; the back-transform dn_i = a_i sum_k e_ki R_k / w_k
+    turns them into population changes, whose second velocity moment is the
+    stress tensor R_ab (kinetic modes drop out: they are orthogonal to every
+    polynomial of degree <= 2)."""
+    c = np.asarray(c)
+    d = int(np.count_nonzero(np.abs(c).sum(axis=0)))
+    q = len(c)
+    mb = np.asarray(m_before, dtype=np.float64).reshape(q, -1)
+    ma = np.asarray(m_after, dtype=np.float64).reshape(q, -1)
+    eq = mb - neq_modes_any(mb, rho0, c, a, e)
+    eq[: 1 + d] = 0.0  # conserved modes: gamma = 1, nothing to subtract
+    g = np.asarray(gammas)[:, None]
+    post = np.where(np.arange(q)[:, None] <= d, mb, eq + g * (mb - eq))
+    Rk = ma.sum(axis=1) - post.sum(axis=1)
+    Rk[: 1 + d] = 0.0
+    dn = np.asarray(a) * (np.asarray(e).T @ (Rk / np.asarray(w)))
+    cc = c[:, :d].astype(float)
+    return np.einsum("i,ia,ib->ab", dn, cc, cc)
+
+
+def macroscopic_stress(R, gb, gs, d=3):
+    """Random stress on the hydrodynamic level, Q = -Rbar/(1 - gs) -
+    delta tr(R)/(d (1 - gb)) with Rbar the traceless part of R (Sec. V)."""
+    tr = np.trace(R)
+    dev = R - tr / d * np.eye(d)
+    return -dev / (1 - gs) - tr / (d * (1 - gb)) * np.eye(d)
+
+
+def macro_stress_covariance(kT, eta, zeta, d=3):
+    """<Q_ab Q_cd> per unit volume and time step, Eq. macrostressfluct with
+    b = h = 1 and m_p cs^2 = kT (Eq. mpeos); returned as a (d,)*4 array."""
+    I = np.eye(d)
+    return 2 * kT * ((zeta - 2 * eta / d) * np.einsum("ab,cd->abcd", I, I)
+                     + eta * (np.einsum("ac,bd->abcd", I, I) + np.einsum("ad,bc->abcd", I, I)))
+
+
+# ---------------------------------------------------------------- any lattice
+def equilibrium_fields(rho, j, c, a):
+    """n_i^eq(rho, u = j / rho) of Eq. derived_equil_distrib with c_s^2 = 1/3
+    for whole fields: rho (N,), j (d, N) -> (q, N)."""
+    c = np.asarray(c, dtype=float)[:, : len(j)]
+    u = np.asarray(j) / rho
+    uc = c @ u
+    uu = (u * u).sum(axis=0)
+    return np.asarray(a)[:, None] * rho * (1 + uc / CS2 + uc * uc / (2 * CS2 ** 2) - uu / (2 * CS2))
+
+
+def neq_modes_any(modes, rho0, c, a, e):
+    """neq_modes for any velocity set: m_k - m_k^eq for the non-conserved
+    modes k > d (m^eq projected from the equilibrium populations), and the
+    conserved modes about their lattice mean.  modes: (q, ...) of n - a rho0."""
+    m = np.array(modes, dtype=np.float64)
+    shp = m.shape
+    m = m.reshape(len(m), -1)
+    d = int(np.count_nonzero(np.abs(np.asarray(c)).sum(axis=0)))
+    rho = rho0 + m[0]
+    neq = equilibrium_fields(rho, m[1:1 + d], c, a)
+    meq = np.asarray(e) @ (neq - np.asarray(a)[:, None] * rho0)
+    out = m - meq
+    for k in range(1 + d):
+        out[k] = m[k] - m[k].mean()
+    return out.reshape(shp)

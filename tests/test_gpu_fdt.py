@@ -9,7 +9,12 @@ equal-time value is fixed by equipartition:
     C(0)   = N rho0 kT,
 
 with A = diag(a_i) (populations are independent with variance mu rho0 a_i
-in the stationary law) and c the velocity component of the mode."""
+in the stationary law) and c the velocity component of the mode.
+
+The random stress of the hydrodynamic equations is checked against its
+Landau-Lifshitz covariance, Eq. macrostressfluct."""
+import itertools
+
 import numpy as np
 import pytest
 import torch
@@ -69,3 +74,40 @@ def test_transverse_momentum_correlation():
         say(f"  tau={t:3d}: C/C0 pred {p / pred[0]:.4f} measured {cm / C[0]:.4f} (se {s / C[0]:.4f})")
         assert abs(cm - p) < 5 * s + 0.02 * pred[0], (t, cm, p, s)
     assert C[0] == pytest.approx(N * kT, rel=0.05)
+
+
+def test_macroscopic_random_stress_covariance():
+    """Sec. V, Eq. macrostressfluct: the box-summed random stress Q of the
+    hydrodynamic equations, measured step by step from the gathered modes of
+    a full run (collision, noise and AA streaming on the device), has the
+    Landau-Lifshitz covariance 2 kT [(zeta - 2 eta/3) d_ab d_cd +
+    eta (d_ac d_bd + d_ad d_bc)] per site, with eta and zeta from Eqs.
+    shearviscosity and bulkviscosity at the mean density."""
+    L, rho0, kT, gb, gs = 8, 1.3, 1e-4, 0.3, 0.5
+    cfg = dict(nx=L, ny=L, nz=L, rho0=rho0, kT=kT, gamma_bulk=gb, gamma_shear=gs, gamma_odd=0.4,
+               gamma_even=-0.3, seed=271828)
+    lat = lbf.Lattice(**cfg, init="thermal")
+    N, T = L ** 3, 20000
+    c, a, e, w = oracle.tables()
+    g = th.mode_gammas(gb, gs, 0.4, -0.3)
+    m = lat.modes().cpu().numpy()
+    rho_bar = rho0 + m[0].astype(np.float64).mean()
+    Q = np.empty((T, 3, 3))
+    for t in range(T):
+        lat.step(1)
+        m1 = lat.modes().cpu().numpy()
+        Q[t] = th.macroscopic_stress(th.box_random_stress(m, m1, rho0, g, c, a, e, w), gb, gs)
+        m = m1
+    lat.close()
+    eta = rho_bar * th.nu_closed_form(gs)
+    zeta = rho_bar * th.zeta_closed_form(gb)
+    want = N * th.macro_stress_covariance(kT, eta, zeta)
+    C = np.einsum("tab,tcd->abcd", Q, Q) / T
+    for idx in [(0, 1, 0, 1), (0, 0, 0, 0), (1, 1, 2, 2), (2, 0, 2, 0)]:
+        say(f"<Q{idx[:2]} Q{idx[2:]}>: measured/predicted {C[idx] / want[idx]:.4f}")
+    assert np.abs(Q.mean(axis=0)).max() < 5 * Q.std(axis=0).max() / np.sqrt(T)
+    for idx in itertools.product(range(3), repeat=4):
+        a, b, c, d = idx
+        prod = Q[:, a, b] * Q[:, c, d]
+        tol = 5 * prod.std() / np.sqrt(T) + 1e-3 * abs(want[idx])
+        assert abs(prod.mean() - want[idx]) < tol, (idx, prod.mean(), want[idx])

@@ -10,6 +10,8 @@
   (4 nu / 3 + zeta / rho) / 2 of the linearised Eq. ce12, and the sound
   speed c_s = 1/sqrt(3) of the equation of state p = rho c_s^2 (Sec. II).
 """
+import itertools
+
 import numpy as np
 import pytest
 
@@ -101,3 +103,39 @@ def test_shear_wave_decay_matches_eigenvalue_1x1xL(tabs):
     lam = abs(th.shear_eigenvalue(L, 1, th.mode_gammas(0.5, gs, 0, 0), c, a, e, w))
     assert amps[1] / amps[0] == pytest.approx(lam, abs=1e-10)
     assert amps[2] / amps[1] == pytest.approx(lam, abs=1e-10)
+
+
+def test_macroscopic_random_stress_covariance():
+    """Sec. V: the random stress Q on the hydrodynamic level, summed over a
+    periodic box and measured from consecutive steps of a full run with
+    streaming, has the Landau-Lifshitz covariance of Eq. macrostressfluct
+    with the viscosities of Eqs. shearviscosity and bulkviscosity, N times
+    the per-site value (sites are independent)."""
+    L, rho0, kT, gb, gs = 3, 1.3, 1e-4, 0.3, 0.5
+    p = oracle.params(L, L, L, rho0=rho0, kT=kT, gamma_bulk=gb, gamma_shear=gs,
+                      gamma_odd=0.4, gamma_even=-0.3, seed=8)
+    n = oracle.init(p, oracle.INIT_THERMAL)
+    N, T = L ** 3, 20000
+    c, a, e, w = oracle.tables()
+    g = th.mode_gammas(gb, gs, 0.4, -0.3)
+    rho_bar = rho0 + oracle.modes(p, n)[0].mean()
+    Q = np.empty((T, 3, 3))
+    m = oracle.modes(p, n)
+    for t in range(T):
+        n = oracle.run(p, n, t, 1)
+        m1 = oracle.modes(p, n)
+        Q[t] = th.macroscopic_stress(th.box_random_stress(m, m1, rho0, g, c, a, e, w), gb, gs)
+        m = m1
+    eta = rho_bar * th.nu_closed_form(gs)
+    zeta = rho_bar * th.zeta_closed_form(gb)
+    want = N * th.macro_stress_covariance(kT, eta, zeta)
+    assert np.abs(Q.mean(axis=0)).max() < 5 * Q.std(axis=0).max() / np.sqrt(T)
+    for idx in itertools.product(range(3), repeat=4):
+        a, b, c, d = idx
+        prod = Q[:, a, b] * Q[:, c, d]
+        tol = 5 * prod.std() / np.sqrt(T) + 1e-3 * abs(want[idx])
+        assert abs(prod.mean() - want[idx]) < tol, (idx, prod.mean(), want[idx])
+    # the worked components: shear, normal, and normal-normal cross terms
+    for (a, b, c, d), w in [((0, 1, 0, 1), 2 * kT * eta), ((0, 0, 0, 0), 2 * kT * (zeta + 4 * eta / 3)),
+                            ((1, 1, 2, 2), 2 * kT * (zeta - 2 * eta / 3))]:
+        assert want[a, b, c, d] == pytest.approx(N * w, rel=1e-12)
