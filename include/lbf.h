@@ -1,41 +1,47 @@
 /*
  * lbf.h -- C ABI of the MI355X (gfx950) fluctuating lattice Boltzmann
- * library: the D3Q19 collide-and-stream update with thermal noise of
- * Duenweg, Schiller & Ladd, "Statistical mechanics of the fluctuating lattice
- * Boltzmann equation" (arXiv:0707.1581).
+ * library: the collide-and-stream update with thermal noise of Duenweg,
+ * Schiller & Ladd, "Statistical mechanics of the fluctuating lattice
+ * Boltzmann equation" (arXiv:0707.1581), on the D3Q19 lattice (basis of
+ * Table II) or the D2Q9 lattice (basis of Table I).
  *
- * What one step computes (per lattice site r, step count t):
- *   1. modes m_k = sum_i e_ki n_i(r) of the 19 populations with the Table II
- *      basis (Sec. III, Eq. modes with the unscaled basis);
- *   2. rho = m_0, j = (m_1, m_2, m_3) (Eqs. defrho, defj) and the
- *      equilibrium stress modes of Eq. derived_equil_distrib (k = 4..9;
- *      the kinetic modes k = 10..18 have no equilibrium part);
- *   3. for every non-conserved mode k = 4..18
+ * What one step computes (per lattice site r, step count t), with q = 19,
+ * d = 3 for D3Q19 and q = 9, d = 2 for D2Q9:
+ *   1. modes m_k = sum_i e_ki n_i(r) of the q populations with the
+ *      lattice's basis (Sec. III, Eq. modes with the unscaled basis);
+ *   2. rho = m_0, j = (m_1 .. m_d) (Eqs. defrho, defj) and the equilibrium
+ *      stress modes of Eq. derived_equil_distrib (the kinetic modes have no
+ *      equilibrium part);
+ *   3. for every non-conserved mode k = d + 1 .. q - 1
  *        m*_k = m_k^eq + gamma_k (m_k - m_k^eq) + sqrt(mu rho w_k (1 - gamma_k^2)) r_k
  *      (Eqs. updaterule and FDT, Sec. IV), with mu = kT / c_s^2 = 3 kT in
- *      lattice units (Sec. VI), w_k the Table II normalisers, rho the local
- *      density and r_k unit Gaussians; conserved modes k <= 3 are unchanged;
+ *      lattice units (Sec. VI), w_k the basis normalisers, rho the local
+ *      density and r_k unit Gaussians; conserved modes k <= d are unchanged;
  *   4. back-transform n*_i = a_i sum_k e_ki m*_k / w_k and push along the
  *      links, n_i(r + c_i, t + 1) = n*_i(r, t), on a periodic box (Eq. LBE).
- * Mode rates: gamma_4 = gamma_bulk, gamma_5..9 = gamma_shear,
+ * Mode rates: D3Q19 gamma_4 = gamma_bulk, gamma_5..9 = gamma_shear,
  * gamma_10..15 = gamma_odd (third-order kinetic modes), gamma_16..18 =
- * gamma_even (fourth-order kinetic modes).
+ * gamma_even (fourth-order kinetic modes); D2Q9 gamma_3 = gamma_bulk,
+ * gamma_4..5 = gamma_shear, gamma_6..7 = gamma_odd, gamma_8 = gamma_even.
  *
- * Velocity order i: 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 = (+1,+1,0)
- * (-1,-1,0) (+1,-1,0) (-1,+1,0) (+1,0,+1) (-1,0,-1) (+1,0,-1) (-1,0,+1)
- * (0,+1,+1) (0,-1,-1) (0,+1,-1) (0,-1,+1); weights a_i = 1/3, 1/18, 1/36
- * (Sec. II).
+ * Velocity order i, D3Q19: 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 =
+ * (+1,+1,0) (-1,-1,0) (+1,-1,0) (-1,+1,0) (+1,0,+1) (-1,0,-1) (+1,0,-1)
+ * (-1,0,+1) (0,+1,+1) (0,-1,-1) (0,+1,-1) (0,-1,+1); weights a_i = 1/3,
+ * 1/18, 1/36 (Sec. II).  D2Q9: 0 rest; 1..4 = +x -x +y -y; 5..8 = (+1,+1)
+ * (-1,-1) (+1,-1) (-1,+1); weights 4/9, 1/9, 1/36 (the three-speed weights
+ * fixed by the isotropy conditions of Sec. II).  c_s^2 = 1/3 for both.
  *
  * Random numbers: Philox4x32-10 keyed on the seed with counter
  * (site, t mod 2^32, call, t >> 32), 24-bit uniforms cut from each three
  * consecutive output words (most significant first), Box-Muller on
- * consecutive uniform pairs (cos first), normal s -> mode 4 + s.  The site
- * is the linear index x + nx (y + ny z) within the lattice, so a replica of
- * a batch draws exactly the numbers of the same lattice run alone.
+ * consecutive uniform pairs (cos first), normal s -> mode d + 1 + s.  The
+ * site is the linear index x + nx (y + ny z) within the lattice, so a
+ * replica of a batch draws exactly the numbers of the same lattice run
+ * alone.
  *
  * State: one caller-owned device buffer holding, for every population i and
  * site, the scaled deviation delta_i = (n_i - a_i rho0) / (a_i rho0) in the
- * storage type (fp32, fp16 or bf16), as 19 planes [i][z][y][x] (x fastest),
+ * storage type (fp32, fp16 or bf16), as q planes [i][z][y][x] (x fastest),
  * updated in place with the AA access pattern: at even t, n_i(r) is held in
  * plane i at site r; at odd t, n_i(r) is held in plane opp(i) at site
  * r - c_i (opp(i) is the index of -c_i).  Callers never need this: all
@@ -71,26 +77,32 @@ enum lb_status {
 
 enum lb_storage { LB_F32 = 0, LB_F16 = 1, LB_BF16 = 2 };
 
+enum lb_lattice {
+  LB_D3Q19 = 0, /* 19 velocities on a cubic lattice, basis of Table II            */
+  LB_D2Q9 = 1   /* 9 velocities on a square lattice, basis of Table I (nz = 1)    */
+};
+
 enum lb_init_kind {
   LB_INIT_REST = 0,    /* n_i = a_i rho0                                          */
   LB_INIT_THERMAL = 1, /* every normalised mode an independent unit Gaussian:     */
                        /* n_i = a_i rho0 + sqrt(mu rho0 a_i) sum_k ehat_ki z_k    */
                        /* (Eqs. xdef, x_s); normals from Philox stream 1          */
   LB_INIT_FIELDS = 2,  /* n_i = n_i^eq(rho, u) by Eq. derived_equil_distrib from  */
-                       /* d_fields (4, nz, ny, nx) fp32 = rho, ux, uy, uz         */
+                       /* d_fields (1 + d, nz, ny, nx) fp32 = rho, ux, uy[, uz]   */
   LB_INIT_KEEP = 3     /* keep the buffer's contents as the state at step t0      */
 };
 
 enum lb_thermal_modes {
   LB_THERMAL_ALL = 0,        /* noise on every non-conserved mode (the paper's    */
                              /* detailed-balance collision, Sec. IV)              */
-  LB_THERMAL_STRESS_ONLY = 1 /* noise on the six stress modes only: the earlier   */
+  LB_THERMAL_STRESS_ONLY = 1 /* noise on the stress modes only: the earlier       */
                              /* model the paper contrasts (kinetic modes get no   */
                              /* noise, violating detailed balance, Sec. IV)       */
 };
 
 typedef struct {
-  int32_t nx, ny, nz;     /* periodic box, each >= 1 (1 makes that axis trivial)  */
+  int32_t nx, ny, nz;     /* periodic box, each >= 1 (1 makes that axis trivial); */
+                          /* nz = 1 for D2Q9                                      */
   int32_t storage;        /* enum lb_storage                                      */
   double rho0;            /* > 0: reference density and deviation base            */
   double kT;              /* >= 0: mu = 3 kT; kT = 0 gives the deterministic update */
@@ -100,12 +112,12 @@ typedef struct {
   double gamma_even;
   uint64_t seed;          /* Philox key                                           */
   int32_t thermal_modes;  /* enum lb_thermal_modes                                */
-  int32_t reserved;       /* must be 0                                            */
+  int32_t lattice;        /* enum lb_lattice (0 = D3Q19)                          */
 } lb_params;
 
 typedef struct lb_ctx lb_ctx; /* opaque, library-owned */
 
-/* Bytes of the state buffer: 19 * nx * ny * nz * sizeof(storage); 0 if the
+/* Bytes of the state buffer: q * nx * ny * nz * sizeof(storage); 0 if the
  * parameters are invalid. */
 size_t lb_state_bytes(const lb_params* p);
 
@@ -122,17 +134,18 @@ int lb_step(lb_ctx* ctx, int64_t nsteps);
 
 /* Parity-resolved gathers into caller-owned fp32 device buffers, each laid
  * out (count, nz, ny, nx):
- *   lb_populations: 19 planes, n_i;
- *   lb_moments:      4 planes, rho, jx, jy, jz (Eqs. defrho, defj);
- *   lb_modes:       19 planes, m_k = sum_i e_ki (n_i - a_i rho0), so m_0 =
- *                   rho - rho0 and m_1..3 = j. */
+ *   lb_populations: q planes, n_i;
+ *   lb_moments:     1 + d planes, rho, jx, jy[, jz] (Eqs. defrho, defj);
+ *   lb_modes:       q planes, m_k = sum_i e_ki (n_i - a_i rho0), so m_0 =
+ *                   rho - rho0 and m_1..d = j. */
 int lb_populations(lb_ctx* ctx, float* d_out);
 int lb_moments(lb_ctx* ctx, float* d_out);
 int lb_modes(lb_ctx* ctx, float* d_out);
 
 /* Synchronising health check: counts sites with a non-finite population or
  * rho <= 0 into *n_bad and writes the lattice sums (sum rho, sum jx, sum jy,
- * sum jz) in fp64 to sums_out[4] (either pointer may be NULL).  Returns
+ * sum jz; sum jz = 0 on D2Q9) in fp64 to sums_out[4] (either pointer may be
+ * NULL).  Returns
  * LB_ESTATE when *n_bad > 0. */
 int lb_check(lb_ctx* ctx, int64_t* n_bad, double* sums_out);
 
@@ -147,15 +160,17 @@ const char* lb_last_error(void);
 
 /* Lattice parameters from physical ones (Sec. VI, choice of parameters).
  * Inputs, in one consistent unit system: lattice spacing b > 0, time step
- * h > 0, mass density rho > 0, shear and bulk viscosities eta > 0 and
- * zeta > 0, and k_B T >= 0.  With the D3Q19 sound speed c_s^2 = (1/3) b^2/h^2,
+ * h > 0, mass density rho > 0 (mass per volume, or per area in 2D), shear
+ * and bulk viscosities eta > 0 and zeta > 0, and k_B T >= 0; p->lattice
+ * must be set on entry and selects the dimension d (3 for D3Q19, 2 for
+ * D2Q9).  With the sound speed c_s^2 = (1/3) b^2/h^2 of both lattices,
  *   eta_hat  = eta h / (rho b^2 / 3),   gamma_shear = (2 eta_hat - 1) / (2 eta_hat + 1),
- *   zeta_hat = zeta h / (rho b^2 / 3),  gamma_bulk  = (3 zeta_hat - 1) / (3 zeta_hat + 1),
- *   mu = k_B T h^2 / ((1/3) b^5)  (mass per site per particle), and in lattice
- * units (b = h = 1, mass unit rho b^3): rho0 = 1 and kT = mu / (3 rho) =
- * k_B T h^2 / (rho b^5).  Writes rho0, kT, gamma_shear and gamma_bulk into
- * *p and leaves its other fields as they are.  Returns LB_EINVAL for
- * invalid inputs (nothing is written). */
+ *   zeta_hat = zeta h / (rho b^2 / 3),  gamma_bulk  = (d zeta_hat - 1) / (d zeta_hat + 1),
+ *   mu = k_B T h^2 / ((1/3) b^(d+2))  (mass per site per particle), and in
+ * lattice units (b = h = 1, mass unit rho b^d): rho0 = 1 and kT = mu / (3 rho)
+ * = k_B T h^2 / (rho b^(d+2)).  Writes rho0, kT, gamma_shear and gamma_bulk
+ * into *p and leaves its other fields as they are.  Returns LB_EINVAL for
+ * invalid inputs or an unknown p->lattice (nothing is written). */
 int lb_params_from_physical(double b, double h, double rho, double eta, double zeta, double kBT,
                             lb_params* p);
 
@@ -169,7 +184,7 @@ size_t lb_batch_pool_bytes(const lb_params* reps, int32_t nrep);
 size_t lb_batch_offset(const lb_params* reps, int32_t nrep, int32_t r);
 
 /* Create an ensemble of nrep >= 1 replicas with their own box, rates,
- * temperature and seed (one storage type for all), laid out in d_pool as by
+ * temperature and seed (one storage type and one lattice for all), laid out in d_pool as by
  * lb_batch_pool_bytes.  init_kind: LB_INIT_REST, LB_INIT_THERMAL or
  * LB_INIT_KEEP (LB_INIT_FIELDS returns LB_EUNSUPPORTED). */
 int lb_batch_init(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_stream,

@@ -45,13 +45,15 @@ int validate(const lb_params* p) {
     if (!(v >= -1.0 && v <= 1.0)) return fail(LB_EINVAL, "every gamma must lie in [-1, 1]");
   if (p->thermal_modes != LB_THERMAL_ALL && p->thermal_modes != LB_THERMAL_STRESS_ONLY)
     return fail(LB_EINVAL, "unknown thermal_modes");
-  if (p->reserved != 0) return fail(LB_EINVAL, "reserved must be 0");
+  if (p->lattice != LB_D3Q19 && p->lattice != LB_D2Q9) return fail(LB_EINVAL, "unknown lattice");
+  if (p->lattice == LB_D2Q9 && p->nz != 1) return fail(LB_EINVAL, "a D2Q9 lattice needs nz = 1");
   const uint64_t n = (uint64_t)p->nx * (uint64_t)p->ny * (uint64_t)p->nz;
   if (n >= (1ull << 32)) return fail(LB_EUNSUPPORTED, "lattices of 2^32 sites or more are not supported");
   return LB_OK;
 }
 
 uint64_t sites_of(const lb_params& p) { return (uint64_t)p.nx * (uint64_t)p.ny * (uint64_t)p.nz; }
+int q_of(int lattice) { return lattice == LB_D2Q9 ? D2Q9::Q : D3Q19::Q; }
 
 // Division by an invariant integer d (Granlund & Montgomery 1994):
 // q = (t + ((n - t) >> s1)) >> s2 with t = mulhi(n, m).
@@ -63,10 +65,10 @@ void div_magic(uint32_t d, uint32_t& m, uint32_t& s1, uint32_t& s2) {
   s2 = l > 0 ? l - 1 : 0;
 }
 
-// Table II normalisers w_k (36 w_k in W36).
-double wk(int k) { return (double)W36[k] / 36.0; }
-
-LatDesc make_desc(const lb_params& p, uint64_t base) {
+// Per-lattice descriptor: geometry, division constants, Philox key and the
+// per-mode coefficients of the model's collision (rates by mode class).
+template <class M>
+LatDesc make_desc_m(const lb_params& p, uint64_t base) {
   LatDesc L;
   std::memset(&L, 0, sizeof(L));
   L.base = base;
@@ -84,19 +86,22 @@ LatDesc make_desc(const lb_params& p, uint64_t base) {
   L.thermal = p.kT > 0.0 ? 1u : 0u;
   L.rho0 = (float)p.rho0;
   const double mu = 3.0 * p.kT;  // kT / c_s^2 in lattice units
-  for (int k = 4; k < Q; ++k) {
-    double g;
-    if (k == 4) g = p.gamma_bulk;
-    else if (k <= 9) g = p.gamma_shear;
-    else if (k <= 15) g = p.gamma_odd;
-    else g = p.gamma_even;
-    const bool noisy = (k <= 9) || p.thermal_modes == LB_THERMAL_ALL;
-    L.ca[k - 4] = (float)(g / (36.0 * wk(k)));
-    if (k <= 9) L.cb[k - 4] = (float)((1.0 - g) / (36.0 * wk(k)));
-    L.cc[k - 4] = noisy ? (float)std::sqrt(mu * (1.0 - g * g) / (wk(k) * p.rho0)) : 0.0f;
+  constexpr int K0 = M::D + 1;
+  for (int k = K0; k < M::Q; ++k) {
+    const int cls = M::CLS[k];  // 1 bulk, 2 shear, 3 odd kinetic, 4 even kinetic
+    const double g = cls == 1 ? p.gamma_bulk : cls == 2 ? p.gamma_shear : cls == 3 ? p.gamma_odd : p.gamma_even;
+    const bool stress = cls <= 2;
+    const bool noisy = stress || p.thermal_modes == LB_THERMAL_ALL;
+    const double wk = (double)M::W36[k] / 36.0;
+    L.ca[k - K0] = (float)(g / (36.0 * wk));
+    if (stress) L.cb[k - K0] = (float)((1.0 - g) / (36.0 * wk));
+    L.cc[k - K0] = noisy ? (float)std::sqrt(mu * (1.0 - g * g) / (wk * p.rho0)) : 0.0f;
   }
-  for (int k = 0; k < Q; ++k) L.ci[k] = (float)std::sqrt(mu / (p.rho0 * wk(k)));
+  for (int k = 0; k < M::Q; ++k) L.ci[k] = (float)std::sqrt(mu / (p.rho0 * ((double)M::W36[k] / 36.0)));
   return L;
+}
+LatDesc make_desc(const lb_params& p, uint64_t base) {
+  return p.lattice == LB_D2Q9 ? make_desc_m<D2Q9>(p, base) : make_desc_m<D3Q19>(p, base);
 }
 
 // Planes of 4 GiB or more need 64-bit offsets (buffer descriptors hold a
@@ -104,78 +109,86 @@ LatDesc make_desc(const lb_params& p, uint64_t base) {
 bool is_wide(const lb_params& p) { return sites_of(p) * elem_size(p.storage) >= (1ull << 32); }
 
 // ---------------------------------------------------------------- kernel tables
-template <int S, int P, bool W>
+template <class M, int S, int P, bool W>
 void* step_ptr_b(int block) {
   switch (block) {
-    case 64: return (void*)&k_step<S, P, W, 64>;
-    case 128: return (void*)&k_step<S, P, W, 128>;
-    case 256: return (void*)&k_step<S, P, W, 256>;
-    case 512: return (void*)&k_step<S, P, W, 512>;
+    case 64: return (void*)&k_step<M, S, P, W, 64>;
+    case 128: return (void*)&k_step<M, S, P, W, 128>;
+    case 256: return (void*)&k_step<M, S, P, W, 256>;
+    case 512: return (void*)&k_step<M, S, P, W, 512>;
   }
   return nullptr;
 }
-template <int S, int P>
-void* step_ptr_w(bool wide, int block) {
-  return wide ? step_ptr_b<S, P, true>(block) : step_ptr_b<S, P, false>(block);
+template <class M, int S>
+void* step_ptr_s(int parity, bool wide, int block) {
+  if (parity) return wide ? step_ptr_b<M, S, 1, true>(block) : step_ptr_b<M, S, 1, false>(block);
+  return wide ? step_ptr_b<M, S, 0, true>(block) : step_ptr_b<M, S, 0, false>(block);
 }
-template <int S>
-void* step_ptr_p(int parity, bool wide, int block) {
-  return parity ? step_ptr_w<S, 1>(wide, block) : step_ptr_w<S, 0>(wide, block);
-}
-void* step_ptr(int storage, int parity, bool wide, int block) {
+template <class M>
+void* step_ptr_m(int storage, int parity, bool wide, int block) {
   switch (storage) {
-    case LB_F32: return step_ptr_p<ST_F32>(parity, wide, block);
-    case LB_F16: return step_ptr_p<ST_F16>(parity, wide, block);
-    case LB_BF16: return step_ptr_p<ST_BF16>(parity, wide, block);
+    case LB_F32: return step_ptr_s<M, ST_F32>(parity, wide, block);
+    case LB_F16: return step_ptr_s<M, ST_F16>(parity, wide, block);
+    case LB_BF16: return step_ptr_s<M, ST_BF16>(parity, wide, block);
   }
   return nullptr;
+}
+void* step_ptr(int lattice, int storage, int parity, bool wide, int block) {
+  return lattice == LB_D2Q9 ? step_ptr_m<D2Q9>(storage, parity, wide, block)
+                            : step_ptr_m<D3Q19>(storage, parity, wide, block);
 }
 
 // Row-tiled step kernels (non-wide lattices only).
-template <int S, int P>
+template <class M, int S, int P>
 void* rows_ptr_b(int block) {
   switch (block) {
-    case 64: return (void*)&k_step_rows<S, P, 64>;
-    case 128: return (void*)&k_step_rows<S, P, 128>;
-    case 256: return (void*)&k_step_rows<S, P, 256>;
-    case 512: return (void*)&k_step_rows<S, P, 512>;
+    case 64: return (void*)&k_step_rows<M, S, P, 64>;
+    case 128: return (void*)&k_step_rows<M, S, P, 128>;
+    case 256: return (void*)&k_step_rows<M, S, P, 256>;
+    case 512: return (void*)&k_step_rows<M, S, P, 512>;
   }
   return nullptr;
 }
-template <int S>
-void* rows_ptr_p(int parity, int block) { return parity ? rows_ptr_b<S, 1>(block) : rows_ptr_b<S, 0>(block); }
-void* rows_ptr(int storage, int parity, int block) {
+template <class M>
+void* rows_ptr_m(int storage, int parity, int block) {
   switch (storage) {
-    case LB_F32: return rows_ptr_p<ST_F32>(parity, block);
-    case LB_F16: return rows_ptr_p<ST_F16>(parity, block);
-    case LB_BF16: return rows_ptr_p<ST_BF16>(parity, block);
+    case LB_F32: return parity ? rows_ptr_b<M, ST_F32, 1>(block) : rows_ptr_b<M, ST_F32, 0>(block);
+    case LB_F16: return parity ? rows_ptr_b<M, ST_F16, 1>(block) : rows_ptr_b<M, ST_F16, 0>(block);
+    case LB_BF16: return parity ? rows_ptr_b<M, ST_BF16, 1>(block) : rows_ptr_b<M, ST_BF16, 0>(block);
   }
   return nullptr;
+}
+void* rows_ptr(int lattice, int storage, int parity, int block) {
+  return lattice == LB_D2Q9 ? rows_ptr_m<D2Q9>(storage, parity, block) : rows_ptr_m<D3Q19>(storage, parity, block);
 }
 
 enum KernelKind { KK_INIT, KK_GATHER, KK_CHECK };
-template <int S, int P, bool W>
+template <class M, int S, int P, bool W>
 void* aux_ptr3(KernelKind kk) {
   switch (kk) {
-    case KK_INIT: return (void*)&k_init<S, P, W>;
-    case KK_GATHER: return (void*)&k_gather<S, P, W>;
-    case KK_CHECK: return (void*)&k_check<S, P, W>;
+    case KK_INIT: return (void*)&k_init<M, S, P, W>;
+    case KK_GATHER: return (void*)&k_gather<M, S, P, W>;
+    case KK_CHECK: return (void*)&k_check<M, S, P, W>;
   }
   return nullptr;
 }
-template <int S, int P>
-void* aux_ptr2(KernelKind kk, bool wide) { return wide ? aux_ptr3<S, P, true>(kk) : aux_ptr3<S, P, false>(kk); }
-template <int S>
-void* aux_ptr1(KernelKind kk, int parity, bool wide) {
-  return parity ? aux_ptr2<S, 1>(kk, wide) : aux_ptr2<S, 0>(kk, wide);
+template <class M, int S>
+void* aux_ptr_s(KernelKind kk, int parity, bool wide) {
+  if (parity) return wide ? aux_ptr3<M, S, 1, true>(kk) : aux_ptr3<M, S, 1, false>(kk);
+  return wide ? aux_ptr3<M, S, 0, true>(kk) : aux_ptr3<M, S, 0, false>(kk);
 }
-void* aux_ptr(KernelKind kk, int storage, int parity, bool wide) {
+template <class M>
+void* aux_ptr_m(KernelKind kk, int storage, int parity, bool wide) {
   switch (storage) {
-    case LB_F32: return aux_ptr1<ST_F32>(kk, parity, wide);
-    case LB_F16: return aux_ptr1<ST_F16>(kk, parity, wide);
-    case LB_BF16: return aux_ptr1<ST_BF16>(kk, parity, wide);
+    case LB_F32: return aux_ptr_s<M, ST_F32>(kk, parity, wide);
+    case LB_F16: return aux_ptr_s<M, ST_F16>(kk, parity, wide);
+    case LB_BF16: return aux_ptr_s<M, ST_BF16>(kk, parity, wide);
   }
   return nullptr;
+}
+void* aux_ptr(KernelKind kk, int lattice, int storage, int parity, bool wide) {
+  return lattice == LB_D2Q9 ? aux_ptr_m<D2Q9>(kk, storage, parity, wide)
+                            : aux_ptr_m<D3Q19>(kk, storage, parity, wide);
 }
 
 }  // namespace
@@ -188,6 +201,7 @@ struct lb_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
   int storage = LB_F32;
+  int lattice = LB_D3Q19;
   bool wide = false;
   std::vector<lb_params> reps;  // one per lattice (1 for a single lattice)
   std::vector<uint64_t> offsets;
@@ -283,8 +297,8 @@ struct StepLaunch {
 };
 StepLaunch step_launch(const lb_ctx* c, int parity) {
   if (c->sched.tiling[parity])
-    return {rows_ptr(c->storage, parity, c->sched.block), c->grid_rows, c->sched.block, c->d_blk_rows};
-  return {step_ptr(c->storage, parity, c->wide, c->sched.block), c->grid, c->sched.block, c->d_blk};
+    return {rows_ptr(c->lattice, c->storage, parity, c->sched.block), c->grid_rows, c->sched.block, c->d_blk_rows};
+  return {step_ptr(c->lattice, c->storage, parity, c->wide, c->sched.block), c->grid, c->sched.block, c->d_blk};
 }
 
 int launch_step(lb_ctx* c, uint32_t t_off, int parity) {
@@ -409,7 +423,7 @@ void free_ctx(lb_ctx* c) {
 int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity) {
   const lb_params& p = c->reps[idx];
   const uint32_t n = (uint32_t)sites_of(p);
-  void* fn = aux_ptr(KK_INIT, c->storage, parity, c->wide);
+  void* fn = aux_ptr(KK_INIT, c->lattice, c->storage, parity, c->wide);
   const LatDesc* L = c->d_lats + idx;
   int k = kind;
   const float* f = d_fields;
@@ -445,7 +459,7 @@ int gather(lb_ctx* c, int what, float* d_out) {
   if (r->reps.size() > 1 && !c->parent) return fail(LB_EINVAL, "gathers on a batch need a view (lb_batch_view)");
   HIP_TRY(hipSetDevice(r->device));
   const uint32_t n = (uint32_t)sites_of(r->reps[v.idx]);
-  void* fn = aux_ptr(KK_GATHER, r->storage, (int)(r->t & 1), r->wide);
+  void* fn = aux_ptr(KK_GATHER, r->lattice, r->storage, (int)(r->t & 1), r->wide);
   const LatDesc* L = r->d_lats + v.idx;
   int w = what;
   float* o = d_out;
@@ -461,7 +475,7 @@ extern "C" {
 
 size_t lb_state_bytes(const lb_params* p) {
   if (validate(p) != LB_OK) return 0;
-  return (size_t)(19 * sites_of(*p) * elem_size(p->storage));
+  return (size_t)(q_of(p->lattice) * sites_of(*p) * elem_size(p->storage));
 }
 
 const char* lb_strerror(int code) {
@@ -497,6 +511,7 @@ int lb_init(const lb_params* p, void* d_state, void* hip_stream, int32_t init_ki
     return fail(LB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
   }
   c->storage = p->storage;
+  c->lattice = p->lattice;
   c->wide = is_wide(*p);
   c->reps.push_back(*p);
   c->offsets.push_back(0);
@@ -536,7 +551,7 @@ int lb_check(lb_ctx* ctx, int64_t* n_bad, double* sums_out) {
   lb_ctx* r = v.root;
   if (r->reps.size() > 1 && !ctx->parent) return fail(LB_EINVAL, "lb_check on a batch needs a view");
   HIP_TRY(hipSetDevice(r->device));
-  void* fn = aux_ptr(KK_CHECK, r->storage, (int)(r->t & 1), r->wide);
+  void* fn = aux_ptr(KK_CHECK, r->lattice, r->storage, (int)(r->t & 1), r->wide);
   const LatDesc* L = r->d_lats + v.idx;
   double* part = r->d_partial;
   void* args[] = {&L, &part};
@@ -573,13 +588,14 @@ int lb_params_from_physical(double b, double h, double rho, double eta, double z
   for (double x : v)
     if (!(x > 0.0) || !std::isfinite(x)) return fail(LB_EINVAL, "b, h, rho, eta and zeta must be finite and > 0");
   if (!(kBT >= 0.0) || !std::isfinite(kBT)) return fail(LB_EINVAL, "k_B T must be finite and >= 0");
-  const double cs2_hat = 1.0 / 3.0;  // D3Q19, Sec. II
-  const double d = 3.0;
+  if (p->lattice != LB_D3Q19 && p->lattice != LB_D2Q9) return fail(LB_EINVAL, "unknown lattice");
+  const double cs2_hat = 1.0 / 3.0;  // both lattices, Sec. II
+  const double d = p->lattice == LB_D2Q9 ? 2.0 : 3.0;
   const double eta_hat = eta * h / (rho * b * b * cs2_hat);
   const double zeta_hat = zeta * h / (rho * b * b * cs2_hat);
   const double mu = kBT * h * h / (cs2_hat * std::pow(b, d + 2.0));  // Sec. VI
   p->rho0 = 1.0;
-  p->kT = cs2_hat * mu / rho;  // lattice units: mass unit rho b^3, mu_lattice = mu / rho
+  p->kT = cs2_hat * mu / rho;  // lattice units: mass unit rho b^d, mu_lattice = mu / rho
   p->gamma_shear = (2.0 * eta_hat - 1.0) / (2.0 * eta_hat + 1.0);
   p->gamma_bulk = (d * zeta_hat - 1.0) / (d * zeta_hat + 1.0);
   return LB_OK;
@@ -612,6 +628,7 @@ int lb_batch_init(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_s
     int rc = validate(&reps[r]);
     if (rc) return rc;
     if (reps[r].storage != reps[0].storage) return fail(LB_EINVAL, "all replicas need the same storage type");
+    if (reps[r].lattice != reps[0].lattice) return fail(LB_EINVAL, "all replicas need the same lattice");
     if (is_wide(reps[r])) return fail(LB_EUNSUPPORTED, "replicas must hold < 4 GiB per population plane");
   }
   if (!d_pool || ((uintptr_t)d_pool & 255)) return fail(LB_EINVAL, "d_pool must be non-NULL and 256-byte aligned");
@@ -627,6 +644,7 @@ int lb_batch_init(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_s
     return fail(LB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
   }
   c->storage = reps[0].storage;
+  c->lattice = reps[0].lattice;
   c->wide = false;
   for (int r = 0; r < nrep; ++r) {
     const uint64_t off = lb_batch_offset(reps, nrep, r);
@@ -674,6 +692,7 @@ int lb_batch_view(lb_ctx* batch, int32_t replica, lb_ctx** view) {
   v->stream = batch->stream;
   v->device = batch->device;
   v->storage = batch->storage;
+  v->lattice = batch->lattice;
   *view = v;
   return LB_OK;
 }

@@ -1,15 +1,16 @@
-// lbf_kernels.h -- gfx950 kernels of the fluctuating D3Q19 lattice Boltzmann
-// update (Duenweg, Schiller & Ladd, arXiv:0707.1581): the fused in-place
+// lbf_kernels.h -- gfx950 kernels of the fluctuating lattice Boltzmann update
+// (Duenweg, Schiller & Ladd, arXiv:0707.1581): the fused in-place
 // collide-and-stream step, initial states, parity-resolved gathers and the
-// health-check reduction.
+// health-check reduction, templated on the lattice model (D3Q19 or D2Q9,
+// see lbf_math.h).
 //
-// One thread per lattice site; all 19 populations of a site are loaded
+// One thread per lattice site; all q populations of a site are loaded
 // before anything is stored, the mode transform, relaxation and noise stay in
 // VGPRs, and nothing goes through LDS.  The in-place update uses the AA access
 // pattern: a step at even t reads plane i at site r and writes the
 // post-collision population i to plane opp(i) at r; a step at odd t reads
 // plane j at r + c_j (which holds n_opp(j)(r)) and writes population j to
-// plane j at r + c_j.  Each thread therefore reads and writes the same 19
+// plane j at r + c_j.  Each thread therefore reads and writes the same q
 // locations, and no two threads touch the same location, so one buffer
 // suffices and no synchronisation is needed inside a step.
 #pragma once
@@ -60,10 +61,12 @@ struct alignas(16) LatDesc {
   uint32_t segs;                    // row tiling: workgroups per x-row (ceil(nx / block))
   uint32_t ds_m, ds_s1, ds_s2;      // division by segs
   float rho0;
-  float ca[15];   // gamma_k / (36 w_k), k = 4..18
-  float cb[6];    // (1 - gamma_k) / (36 w_k), k = 4..9
-  float cc[15];   // sqrt(mu (1 - gamma_k^2) / (w_k rho0)), k = 4..18; 0 if unthermalised
-  float ci[19];   // sqrt(mu / (rho0 w_k)): thermal initial state
+  // per-mode coefficients, indexed from the first non-conserved mode K0 = d + 1
+  // (D3Q19 uses all entries, D2Q9 the first 6, 3, 6 and 9)
+  float ca[15];   // gamma_k / (36 w_k), k = K0..q-1
+  float cb[6];    // (1 - gamma_k) / (36 w_k), stress modes k = K0..K0+NSTRESS-1
+  float cc[15];   // sqrt(mu (1 - gamma_k^2) / (w_k rho0)), k = K0..q-1; 0 if unthermalised
+  float ci[19];   // sqrt(mu / (rho0 w_k)), k = 0..q-1: thermal initial state
 };
 static_assert(sizeof(LatDesc) % 16 == 0, "LatDesc alignment");
 
@@ -126,13 +129,16 @@ __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float k2, flo
 constexpr float NEG_2LN2 = -1.3862943611198906f;  // -2 ln 2: sqrt(-2 ln u) = sqrt(-2 ln2 log2 u)
 
 // ---------------------------------------------------------------- addressing
-// Element offsets o_j of site r + c_j (periodic), j = 0..18.
-template <class Off>
-__device__ __forceinline__ void neighbour_offsets(const LatDesc& L, uint32_t site, Off o[Q]) {
+// Element offsets o_j of site r + c_j (periodic), j = 0..q-1.
+template <class M, class Off>
+__device__ __forceinline__ void neighbour_offsets(const LatDesc& L, uint32_t site, Off o[M::Q]) {
   const uint32_t zy = fastdiv(site, L.dx_m, L.dx_s1, L.dx_s2);
   const uint32_t x = site - zy * L.nx;
-  const uint32_t z = fastdiv(zy, L.dy_m, L.dy_s1, L.dy_s2);
-  const uint32_t y = zy - z * L.ny;
+  uint32_t z = 0, y = zy;  // a 2D lattice has nz = 1
+  if constexpr (M::D == 3) {
+    z = fastdiv(zy, L.dy_m, L.dy_s1, L.dy_s2);
+    y = zy - z * L.ny;
+  }
   // signed steps in 32-bit wrap-around arithmetic; the sums land in [0, N)
   const uint32_t xm = (x == 0) ? L.wx : 0xFFFFFFFFu;
   const uint32_t xp = (x == L.wx) ? 0u - L.wx : 1u;
@@ -141,14 +147,14 @@ __device__ __forceinline__ void neighbour_offsets(const LatDesc& L, uint32_t sit
   const uint32_t zm = (z == 0) ? L.wz : 0u - L.nxy;
   const uint32_t zp = (z * L.nxy == L.wz) ? 0u - L.wz : L.nxy;
 #pragma unroll
-  for (int j = 0; j < Q; ++j) {
+  for (int j = 0; j < M::Q; ++j) {
     uint32_t s = site;
-    if (CY[j] > 0) s += yp;
-    if (CY[j] < 0) s += ym;
-    if (CZ[j] > 0) s += zp;
-    if (CZ[j] < 0) s += zm;
-    if (CX[j] > 0) s += xp;
-    if (CX[j] < 0) s += xm;
+    if (M::CY[j] > 0) s += yp;
+    if (M::CY[j] < 0) s += ym;
+    if (M::CZ[j] > 0) s += zp;
+    if (M::CZ[j] < 0) s += zm;
+    if (M::CX[j] > 0) s += xp;
+    if (M::CX[j] < 0) s += xm;
     o[j] = (Off)s;
   }
 }
@@ -171,10 +177,10 @@ __device__ __forceinline__ void neighbour_offsets(const LatDesc& L, uint32_t sit
 constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
 constexpr int RAW_BUFFER_WORD3 = 0x00020000;
 
-template <int S, int P> struct CachePolicy {
+template <class M, int S, int P> struct CachePolicy {
   // plane j of the odd step is accessed at r + c_j: shifted along x iff c_jx != 0
-  static constexpr bool nt_load(int j) { return P == 0 || CX[j] == 0; }
-  static constexpr bool nt_store(int j) { return P == 0 || CX[j] == 0; }
+  static constexpr bool nt_load(int j) { return P == 0 || M::CX[j] == 0; }
+  static constexpr bool nt_store(int j) { return P == 0 || M::CX[j] == 0; }
 };
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const LatDesc& L, int plane, uint32_t esize) {
@@ -242,77 +248,76 @@ __device__ __forceinline__ void st_sel(const LatDesc& L, int plane, Off o, T v, 
   if (nt) st<T, CPOL_NT>(L, plane, o, v); else st<T, 0>(L, plane, o, v);
 }
 
-// Load the 19 populations (as d_i) of site r of the state at parity P.
-template <int S, int P, class Off>
-__device__ __forceinline__ void load_site(const LatDesc& L, uint32_t site, float d[Q], Off o[Q]) {
+// Load the q populations (as d_i) of site r of the state at parity P.
+template <class M, int S, int P, class Off>
+__device__ __forceinline__ void load_site(const LatDesc& L, uint32_t site, float d[M::Q], Off o[M::Q]) {
   using C = Codec<S>;
+  using CP = CachePolicy<M, S, P>;
   if (P == 0) {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) o[j] = (Off)site;
+    for (int j = 0; j < M::Q; ++j) o[j] = (Off)site;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = C::dec(ld_sel<typename C::T>(L, i, o[i], CachePolicy<S, P>::nt_load(i)));
+    for (int i = 0; i < M::Q; ++i) d[i] = C::dec(ld_sel<typename C::T>(L, i, o[i], CP::nt_load(i)));
   } else {
-    neighbour_offsets(L, site, o);
+    neighbour_offsets<M>(L, site, o);
     // plane j at r + c_j holds population opp(j) of site r
 #pragma unroll
-    for (int j = 0; j < Q; ++j) d[OPP[j]] = C::dec(ld_sel<typename C::T>(L, j, o[j], CachePolicy<S, P>::nt_load(j)));
+    for (int j = 0; j < M::Q; ++j) d[M::OPP[j]] = C::dec(ld_sel<typename C::T>(L, j, o[j], CP::nt_load(j)));
   }
 }
 
 // ---------------------------------------------------------------- collision
-// Post-collision d*_i of one site from its pre-collision d_i, in place.
-// Equilibrium stress modes in units of rho0/36 (R = 36 rho / rho0):
-// mu_4 = |j|^2 / R, mu_5 = (2 jx^2 - jy^2 - jz^2) / R, mu_6 = (jy^2 - jz^2) / R,
-// mu_7..9 = jx jy / R, jy jz / R, jz jx / R (the stress modes of Eq.
-// derived_equil_distrib with sigma_2 = c_s^2 = 1/3; kinetic modes have none).
-__device__ __forceinline__ void collide(const LatDesc& L, float d[Q], uint32_t site, uint32_t tlo,
+// Post-collision d*_i of one site from its pre-collision d_i, in place:
+// forward transform, equilibrium stress modes (the model's stress_eq),
+// relaxation m* = m^eq + gamma_k (m - m^eq) of every non-conserved mode and,
+// when kT > 0, noise sqrt(mu rho w_k (1 - gamma_k^2)) r_k (Sec. IV), then the
+// back-transform.  Noise: the q - d - 1 non-conserved modes take, in table
+// order, the unit normals of stream 0 of (seed, site, t) (Philox words ->
+// 24-bit chunks -> Box-Muller pairs).
+template <class M>
+__device__ __forceinline__ void collide(const LatDesc& L, float d[M::Q], uint32_t site, uint32_t tlo,
                                         uint32_t thi) {
+  constexpr int Q = M::Q, K0 = M::D + 1, NS = M::NSTRESS;
   float mu[Q];
-  forward_modes(d, mu);
+  M::forward(d, mu);
 
   const float R = 36.0f + mu[0];
   const float iR = __builtin_amdgcn_rcpf(R);
-  const float vx = mu[1] * iR, vy = mu[2] * iR, vz = mu[3] * iR;
-  const float xx = mu[1] * vx, yy = mu[2] * vy, zz = mu[3] * vz;
-  float eq[6];
-  eq[0] = (xx + yy) + zz;
-  eq[1] = (2.0f * xx - yy) - zz;
-  eq[2] = yy - zz;
-  eq[3] = mu[1] * vy;
-  eq[4] = mu[2] * vz;
-  eq[5] = mu[3] * vx;
+  float eq[NS];
+  M::stress_eq(mu, iR, eq);
 
   float nu[Q];
   nu[0] = mu[0] * (1.0f / 36.0f);
-  nu[1] = mu[1] * (1.0f / 12.0f);
-  nu[2] = mu[2] * (1.0f / 12.0f);
-  nu[3] = mu[3] * (1.0f / 12.0f);
+#pragma unroll
+  for (int k = 1; k < K0; ++k) nu[k] = mu[k] * (1.0f / 12.0f);
   if (L.thermal) {
+    constexpr int NP = (Q - K0 + 1) / 2;    // Box-Muller pairs
+    constexpr int NT = (2 * NP + 3) / 4;    // word triples, four chunks each
+    constexpr int NC = (3 * NT + 3) / 4;    // Philox calls
     // every noise amplitude scales with sqrt(rho / rho0) = sqrt(R / 36)
     const float k2 = (NEG_2LN2 / 36.0f) * R;
-    uint32_t w[12];
-    philox10(site, tlo, 0u, thi, L.key0, L.key1, w);
-    philox10(site, tlo, 1u, thi, L.key0, L.key1, w + 4);
-    philox10(site, tlo, 2u, thi, L.key0, L.key1, w + 8);
-    uint32_t ch[16];
+    uint32_t w[4 * NC];
 #pragma unroll
-    for (int g = 0; g < 4; ++g) chunks4(w[3 * g], w[3 * g + 1], w[3 * g + 2], ch + 4 * g);
-    float z[16];
+    for (int c = 0; c < NC; ++c) philox10(site, tlo, (uint32_t)c, thi, L.key0, L.key1, w + 4 * c);
+    uint32_t ch[4 * NT];
 #pragma unroll
-    for (int p = 0; p < 8; ++p) box_muller(ch[2 * p], ch[2 * p + 1], k2, z[2 * p], z[2 * p + 1]);
+    for (int g = 0; g < NT; ++g) chunks4(w[3 * g], w[3 * g + 1], w[3 * g + 2], ch + 4 * g);
+    float z[2 * NP];
 #pragma unroll
-    for (int k = 4; k < 10; ++k)
-      nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], __builtin_fmaf(L.cb[k - 4], eq[k - 4], L.cc[k - 4] * z[k - 4]));
+    for (int p = 0; p < NP; ++p) box_muller(ch[2 * p], ch[2 * p + 1], k2, z[2 * p], z[2 * p + 1]);
 #pragma unroll
-    for (int k = 10; k < Q; ++k) nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], L.cc[k - 4] * z[k - 4]);
+    for (int k = K0; k < K0 + NS; ++k)
+      nu[k] = __builtin_fmaf(L.ca[k - K0], mu[k], __builtin_fmaf(L.cb[k - K0], eq[k - K0], L.cc[k - K0] * z[k - K0]));
+#pragma unroll
+    for (int k = K0 + NS; k < Q; ++k) nu[k] = __builtin_fmaf(L.ca[k - K0], mu[k], L.cc[k - K0] * z[k - K0]);
   } else {
 #pragma unroll
-    for (int k = 4; k < 10; ++k) nu[k] = __builtin_fmaf(L.ca[k - 4], mu[k], L.cb[k - 4] * eq[k - 4]);
+    for (int k = K0; k < K0 + NS; ++k) nu[k] = __builtin_fmaf(L.ca[k - K0], mu[k], L.cb[k - K0] * eq[k - K0]);
 #pragma unroll
-    for (int k = 10; k < Q; ++k) nu[k] = L.ca[k - 4] * mu[k];
+    for (int k = K0 + NS; k < Q; ++k) nu[k] = L.ca[k - K0] * mu[k];
   }
 
-  back_transform(nu, d);
+  M::back(nu, d);
 }
 
 // ---------------------------------------------------------------- tile lookup
@@ -349,12 +354,13 @@ __device__ __forceinline__ uint32_t find_lattice(const uint32_t* __restrict__ bl
 // ---------------------------------------------------------------- step kernel
 // One fused collide-and-stream step at step count t = *d_t + t_off with
 // parity P = t & 1, for every site of every lattice in lats[0..nlat).
-template <int S, int P, bool WIDE, int BLOCK>
+template <class M, int S, int P, bool WIDE, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
        uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   using C = Codec<S>;
+  constexpr int Q = M::Q;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, remap);
   uint32_t l = 0;
   if (nlat > 1) l = find_lattice(blk, nlat, b);
@@ -366,14 +372,15 @@ k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint3
 
   float d[Q];
   Off o[Q];
-  load_site<S, P>(L, site, d, o);
-  collide(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
+  load_site<M, S, P>(L, site, d, o);
+  collide<M>(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
   if (P == 0) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st_sel(L, OPP[i], o[i], C::enc(d[i]), CachePolicy<S, 0>::nt_store(OPP[i]));
+    for (int i = 0; i < Q; ++i)
+      st_sel(L, M::OPP[i], o[i], C::enc(d[i]), CachePolicy<M, S, 0>::nt_store(M::OPP[i]));
   } else {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) st_sel(L, j, o[j], C::enc(d[j]), CachePolicy<S, 1>::nt_store(j));
+    for (int j = 0; j < Q; ++j) st_sel(L, j, o[j], C::enc(d[j]), CachePolicy<M, S, 1>::nt_store(j));
   }
 }
 
@@ -385,12 +392,14 @@ k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint3
 // instruction as its scalar offset); each lane only computes x and its two
 // periodic x-neighbours.  Lanes past the end of the row stay idle, so this
 // suits rows of at least a few workgroups' worth of sites.
-template <int S, int P, int BLOCK>
+template <class M, int S, int P, int BLOCK>
 __global__ void __launch_bounds__(BLOCK)
 k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
             uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
   using C = Codec<S>;
   using T = typename C::T;
+  using CP = CachePolicy<M, S, 1>;
+  constexpr int Q = M::Q;
   constexpr uint32_t ES = sizeof(T);
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, remap);
   uint32_t l = 0;
@@ -401,8 +410,11 @@ k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
   const uint32_t row = fastdiv(bl, L.ds_m, L.ds_s1, L.ds_s2);
   const uint32_t x = (bl - row * L.segs) * BLOCK + threadIdx.x;
   if (x >= L.nx) return;
-  const uint32_t z = fastdiv(row, L.dy_m, L.dy_s1, L.dy_s2);
-  const uint32_t y = row - z * L.ny;
+  uint32_t z = 0, y = row;  // a 2D lattice has nz = 1
+  if constexpr (M::D == 3) {
+    z = fastdiv(row, L.dy_m, L.dy_s1, L.dy_s2);
+    y = row - z * L.ny;
+  }
   const uint64_t t = *d_t + t_off;
   const uint32_t site = x + row * L.nx;
 
@@ -427,31 +439,31 @@ k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       uint32_t ro = r0;
-      if (CY[j] > 0) ro += yp;
-      if (CY[j] < 0) ro += ym;
-      if (CZ[j] > 0) ro += zp;
-      if (CZ[j] < 0) ro += zm;
-      const uint32_t vx = CX[j] > 0 ? bxp : (CX[j] < 0 ? bxm : bx);
-      const T v = CachePolicy<S, 1>::nt_load(j) ? Raw<T>::template ld<CPOL_NT>(plane_rsrc(L, j, ES), vx, ro * ES)
-                                                 : Raw<T>::template ld<0>(plane_rsrc(L, j, ES), vx, ro * ES);
-      d[OPP[j]] = C::dec(v);
+      if (M::CY[j] > 0) ro += yp;
+      if (M::CY[j] < 0) ro += ym;
+      if (M::CZ[j] > 0) ro += zp;
+      if (M::CZ[j] < 0) ro += zm;
+      const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
+      const T v = CP::nt_load(j) ? Raw<T>::template ld<CPOL_NT>(plane_rsrc(L, j, ES), vx, ro * ES)
+                                 : Raw<T>::template ld<0>(plane_rsrc(L, j, ES), vx, ro * ES);
+      d[M::OPP[j]] = C::dec(v);
     }
   }
-  collide(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
+  collide<M>(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
   if (P == 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      Raw<T>::template st<CPOL_NT>(plane_rsrc(L, OPP[i], ES), bx, C::enc(d[i]), r0 * ES);
+      Raw<T>::template st<CPOL_NT>(plane_rsrc(L, M::OPP[i], ES), bx, C::enc(d[i]), r0 * ES);
   } else {
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
       uint32_t ro = r0;
-      if (CY[j] > 0) ro += yp;
-      if (CY[j] < 0) ro += ym;
-      if (CZ[j] > 0) ro += zp;
-      if (CZ[j] < 0) ro += zm;
-      const uint32_t vx = CX[j] > 0 ? bxp : (CX[j] < 0 ? bxm : bx);
-      if (CachePolicy<S, 1>::nt_store(j)) Raw<T>::template st<CPOL_NT>(plane_rsrc(L, j, ES), vx, C::enc(d[j]), ro * ES);
+      if (M::CY[j] > 0) ro += yp;
+      if (M::CY[j] < 0) ro += ym;
+      if (M::CZ[j] > 0) ro += zp;
+      if (M::CZ[j] < 0) ro += zm;
+      const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
+      if (CP::nt_store(j)) Raw<T>::template st<CPOL_NT>(plane_rsrc(L, j, ES), vx, C::enc(d[j]), ro * ES);
       else Raw<T>::template st<0>(plane_rsrc(L, j, ES), vx, C::enc(d[j]), ro * ES);
     }
   }
@@ -466,27 +478,28 @@ __global__ void k_set_t(uint64_t* d_t, uint64_t t) {
 }
 
 // ---------------------------------------------------------------- initial states
-// Store the 19 d_i of site r as the state at parity P.
-template <int S, int P, class Off>
-__device__ __forceinline__ void store_site(const LatDesc& L, uint32_t site, const float d[Q]) {
+// Store the q d_i of site r as the state at parity P.
+template <class M, int S, int P, class Off>
+__device__ __forceinline__ void store_site(const LatDesc& L, uint32_t site, const float d[M::Q]) {
   using C = Codec<S>;
   if (P == 0) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st<typename C::T, 0>(L, i, (Off)site, C::enc(d[i]));
+    for (int i = 0; i < M::Q; ++i) st<typename C::T, 0>(L, i, (Off)site, C::enc(d[i]));
   } else {
-    Off o[Q];
-    neighbour_offsets(L, site, o);
+    Off o[M::Q];
+    neighbour_offsets<M>(L, site, o);
 #pragma unroll
-    for (int j = 0; j < Q; ++j) st<typename C::T, 0>(L, j, o[j], C::enc(d[OPP[j]]));
+    for (int j = 0; j < M::Q; ++j) st<typename C::T, 0>(L, j, o[j], C::enc(d[M::OPP[j]]));
   }
 }
 
 // kind 0: rest; kind 1: thermal (stream 1, normal k -> mode k);
-// kind 2: n_i^eq(rho, u) from fields (4, nz, ny, nx).
-template <int S, int P, bool WIDE>
+// kind 2: n_i^eq(rho, u) from fields (1 + d, nz, ny, nx) = rho, ux, uy[, uz].
+template <class M, int S, int P, bool WIDE>
 __global__ void __launch_bounds__(256)
 k_init(const LatDesc* __restrict__ Lp, int kind, const float* __restrict__ fields) {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  constexpr int Q = M::Q;
   const LatDesc& L = *Lp;
   const uint32_t site = blockIdx.x * 256u + threadIdx.x;
   if (site >= L.nsites) return;
@@ -495,63 +508,67 @@ k_init(const LatDesc* __restrict__ Lp, int kind, const float* __restrict__ field
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = 0.0f;
   } else if (kind == 1) {
-    uint32_t w[16];
+    constexpr int NP = (Q + 1) / 2;         // Box-Muller pairs
+    constexpr int NT = (2 * NP + 3) / 4;    // word triples
+    constexpr int NC = (3 * NT + 3) / 4;    // Philox calls
+    uint32_t w[4 * NC];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) philox10(site, 0u, (1u << 16) | (uint32_t)c, 0u, L.key0, L.key1, w + 4 * c);
-    uint32_t ch[20];
+    for (int c = 0; c < NC; ++c) philox10(site, 0u, (1u << 16) | (uint32_t)c, 0u, L.key0, L.key1, w + 4 * c);
+    uint32_t ch[4 * NT];
 #pragma unroll
-    for (int g = 0; g < 5; ++g) chunks4(w[3 * g], w[3 * g + 1], w[3 * g + 2], ch + 4 * g);
-    float z[20];
+    for (int g = 0; g < NT; ++g) chunks4(w[3 * g], w[3 * g + 1], w[3 * g + 2], ch + 4 * g);
+    float z[2 * NP];
 #pragma unroll
-    for (int p = 0; p < 10; ++p) box_muller(ch[2 * p], ch[2 * p + 1], NEG_2LN2, z[2 * p], z[2 * p + 1]);
+    for (int p = 0; p < NP; ++p) box_muller(ch[2 * p], ch[2 * p + 1], NEG_2LN2, z[2 * p], z[2 * p + 1]);
     float nu[Q];
 #pragma unroll
     for (int k = 0; k < Q; ++k) nu[k] = L.ci[k] * z[k];
-    back_transform(nu, d);
+    M::back(nu, d);
   } else {
     const uint64_t N = L.plane;
-    const float rho = fields[site], ux = fields[N + site], uy = fields[2 * N + site], uz = fields[3 * N + site];
+    const float rho = fields[site], ux = fields[N + site], uy = fields[2 * N + site];
+    const float uz = (M::D == 3) ? fields[3 * N + site] : 0.0f;
     // d_i = rho/rho0 (1 + 3 u.c + 9/2 (u.c)^2 - 3/2 u^2) - 1
     const float dr = rho / L.rho0 - 1.0f;
-    const float uu = 1.5f * (ux * ux + uy * uy + uz * uz);
+    const float uu = (M::D == 3) ? 1.5f * (ux * ux + uy * uy + uz * uz) : 1.5f * (ux * ux + uy * uy);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const float uc = CX[i] * ux + CY[i] * uy + CZ[i] * uz;
+      const float uc = (M::D == 3) ? M::CX[i] * ux + M::CY[i] * uy + M::CZ[i] * uz : M::CX[i] * ux + M::CY[i] * uy;
       const float poly = __builtin_fmaf(4.5f * uc, uc, 3.0f * uc) - uu;
       d[i] = __builtin_fmaf(1.0f + dr, poly, dr);
     }
   }
-  store_site<S, P, Off>(L, site, d);
+  store_site<M, S, P, Off>(L, site, d);
 }
 
 // ---------------------------------------------------------------- gathers
-// what: 0 populations n_i (19 planes), 1 moments rho, j (4 planes), 2 modes m_k (19 planes).
-template <int S, int P, bool WIDE>
+// what: 0 populations n_i (q planes), 1 moments rho, j (1 + d planes), 2 modes m_k (q planes).
+template <class M, int S, int P, bool WIDE>
 __global__ void __launch_bounds__(256)
 k_gather(const LatDesc* __restrict__ Lp, int what, float* __restrict__ out) {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  constexpr int Q = M::Q;
   const LatDesc& L = *Lp;
   const uint32_t site = blockIdx.x * 256u + threadIdx.x;
   if (site >= L.nsites) return;
   const uint64_t N = L.plane;
   float d[Q];
   Off o[Q];
-  load_site<S, P>(L, site, d, o);
+  load_site<M, S, P>(L, site, d, o);
   if (what == 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const float ar = (i == 0 ? (1.0f / 3.0f) : (i <= 6 ? (1.0f / 18.0f) : (1.0f / 36.0f))) * L.rho0;
+      const float ar = (M::A36[i] / 36.0f) * L.rho0;
       out[i * N + site] = __builtin_fmaf(ar, d[i], ar);
     }
   } else {
     float mu[Q];
-    forward_modes(d, mu);
+    M::forward(d, mu);
     const float s = L.rho0 * (1.0f / 36.0f);
     if (what == 1) {
       out[site] = __builtin_fmaf(s, mu[0], L.rho0);
-      out[N + site] = s * mu[1];
-      out[2 * N + site] = s * mu[2];
-      out[3 * N + site] = s * mu[3];
+#pragma unroll
+      for (int a = 1; a <= M::D; ++a) out[a * N + site] = s * mu[a];
     } else {
 #pragma unroll
       for (int k = 0; k < Q; ++k) out[k * N + site] = s * mu[k];
@@ -564,28 +581,28 @@ k_gather(const LatDesc* __restrict__ Lp, int what, float* __restrict__ out) {
 // a grid-stride loop; a second one-block kernel reduces the partials in a
 // fixed order, so the result is deterministic.
 constexpr int CHECK_BLOCKS = 512;
-template <int S, int P, bool WIDE>
+template <class M, int S, int P, bool WIDE>
 __global__ void __launch_bounds__(256)
 k_check(const LatDesc* __restrict__ Lp, double* __restrict__ partial) {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  constexpr int Q = M::Q;
   const LatDesc& L = *Lp;
-  double acc[5] = {0, 0, 0, 0, 0};
+  double acc[5] = {0, 0, 0, 0, 0};  // bad sites, rho - rho0, jx, jy, jz (0 in 2D)
   for (uint32_t site = blockIdx.x * 256u + threadIdx.x; site < L.nsites; site += gridDim.x * 256u) {
     float d[Q];
     Off o[Q];
-    load_site<S, P>(L, site, d, o);
+    load_site<M, S, P>(L, site, d, o);
     bool finite = true;
 #pragma unroll
     for (int i = 0; i < Q; ++i) finite = finite && __builtin_isfinite(d[i]);
     float mu[Q];
-    forward_modes(d, mu);
+    M::forward(d, mu);
     const float s = L.rho0 * (1.0f / 36.0f);
     const float rho = __builtin_fmaf(s, mu[0], L.rho0);
     if (!finite || !(rho > 0.0f)) acc[0] += 1.0;
     acc[1] += (double)(s * mu[0]);
-    acc[2] += (double)(s * mu[1]);
-    acc[3] += (double)(s * mu[2]);
-    acc[4] += (double)(s * mu[3]);
+#pragma unroll
+    for (int a = 1; a <= M::D; ++a) acc[1 + a] += (double)(s * mu[a]);
   }
   __shared__ double red[5][256];
 #pragma unroll

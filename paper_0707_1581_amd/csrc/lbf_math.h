@@ -1,25 +1,26 @@
-// lbf_math.h -- register-resident D3Q19 mode transforms.
+// lbf_math.h -- register-resident mode transforms of the two lattice models,
+// D3Q19 (basis of Table II) and D2Q9 (basis of Table I).
 //
-// The state is the scaled deviation d_i = (n_i - a_i rho0) / (a_i rho0)
-// (a_i = 1/3, 1/18, 1/36 for the rest, axis and diagonal velocities, Sec. II).
-// Working in units of rho0 / 36, the unscaled Table II modes m_k = sum_i e_ki n_i
+// The state is the scaled deviation d_i = (n_i - a_i rho0) / (a_i rho0).
+// Working in units of rho0 / 36, the unscaled modes m_k = sum_i e_ki n_i
 // (Sec. III) of the deviation n_i - a_i rho0 become
 //     mu_k = 36 m_k / rho0 = sum_i (36 a_i) e_ki d_i,
-// with the integer weights 36 a_i = 12, 2, 1, and the back-transform
-// n_i = a_i sum_k e_ki m_k / w_k (completeness of the orthonormal basis,
-// Eqs. orthogonality and evectors_orthonormal) becomes
+// with integer weights 36 a_i (12, 2, 1 for D3Q19; 16, 4, 1 for D2Q9), and
+// the back-transform n_i = a_i sum_k e_ki m_k / w_k (completeness of the
+// orthonormal basis, Eqs. orthogonality and evectors_orthonormal) becomes
 //     d_i = sum_k e_ki nu_k,   nu_k = mu_k / (36 w_k).
 //
-// Opposite velocities i, opp(i) share the even-parity rows of Table II
-// (k = 0, 4..9, 16..18) and have opposite odd-parity rows (k = 1..3,
-// 10..15), so both transforms run on the nine pair sums s = d_i + d_opp(i)
-// and differences d = d_i - d_opp(i) (first member of each pair has the
-// positive component): a 10 x 10 even block and a 9 x 9 odd block with
-// small integer coefficients, written out term by term below.
+// Opposite velocities i, opp(i) share the even-parity rows of the basis and
+// have opposite odd-parity rows, so both transforms run on the pair sums
+// s = d_i + d_opp(i) and differences d = d_i - d_opp(i) (first member of
+// each pair has the positive leading component): one block of small integer
+// coefficients per parity, written out term by term below.
 //
-// Velocity order: 0 rest; 1..6 = +x -x +y -y +z -z; 7/8 = +-(1,1,0);
-// 9/10 = +-(1,-1,0); 11/12 = +-(1,0,1); 13/14 = +-(1,0,-1);
-// 15/16 = +-(0,1,1); 17/18 = +-(0,1,-1).
+// Each model also gives the equilibrium values of its stress modes (the
+// only non-conserved modes with a non-zero equilibrium part: the kinetic
+// modes are orthogonal to every polynomial of degree <= 2) from mu_1..mu_d
+// and 1 / R, R = 36 rho / rho0, by the stress of Eq. derived_equil_distrib
+// with sigma_2 = c_s^2 = 1/3.
 #pragma once
 
 #if defined(__HIPCC__)
@@ -30,18 +31,44 @@
 
 namespace lbf {
 
-constexpr int Q = 19;
-constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
-constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
-constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
-constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+// ================================================================ D3Q19
+// Velocity order: 0 rest; 1..6 = +x -x +y -y +z -z; 7/8 = +-(1,1,0);
+// 9/10 = +-(1,-1,0); 11/12 = +-(1,0,1); 13/14 = +-(1,0,-1);
+// 15/16 = +-(0,1,1); 17/18 = +-(0,1,-1).  Modes (Table II): 0..3
+// conserved, 4 bulk, 5..9 shear, 10..15 odd kinetic, 16..18 even kinetic.
+struct D3Q19 {
+  static constexpr int Q = 19, D = 3;
+  static constexpr int NSTRESS = 6;  // stress modes k = D + 1 .. D + NSTRESS
+  static constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  static constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  static constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  static constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+  // 36 a_i (Sec. II: 1/3, 1/18, 1/36) and 36 w_k of Table II (w_k = sum_i a_i e_ki^2)
+  static constexpr float A36[Q] = {12, 2, 2, 2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1};
+  static constexpr float W36[Q] = {36, 12, 12, 12, 24, 48, 16, 4, 4, 4, 24, 24, 24, 8, 8, 8, 72, 48, 16};
+  // mode class: 0 conserved, 1 bulk, 2 shear, 3 odd kinetic, 4 even kinetic
+  static constexpr int CLS[Q] = {0, 0, 0, 0, 1, 2, 2, 2, 2, 2, 3, 3, 3, 3, 3, 3, 4, 4, 4};
 
-// 36 w_k of Table II (w_k = sum_i a_i e_ki^2).
-constexpr float W36[Q] = {36, 12, 12, 12, 24, 48, 16, 4, 4, 4, 24, 24, 24, 8, 8, 8, 72, 48, 16};
+  template <class F> static LBF_HD void forward(const F d[Q], F mu[Q]);
+  template <class F> static LBF_HD void back(const F nu[Q], F d[Q]);
+  // equilibrium stress modes in units of rho0/36:
+  // mu_4 = |j|^2 / R, mu_5 = (2 jx^2 - jy^2 - jz^2) / R, mu_6 = (jy^2 - jz^2) / R,
+  // mu_7..9 = jx jy / R, jy jz / R, jz jx / R
+  template <class F> static LBF_HD void stress_eq(const F mu[Q], F iR, F eq[NSTRESS]) {
+    const F vx = mu[1] * iR, vy = mu[2] * iR, vz = mu[3] * iR;
+    const F xx = mu[1] * vx, yy = mu[2] * vy, zz = mu[3] * vz;
+    eq[0] = (xx + yy) + zz;
+    eq[1] = (F(2) * xx - yy) - zz;
+    eq[2] = yy - zz;
+    eq[3] = mu[1] * vy;
+    eq[4] = mu[2] * vz;
+    eq[5] = mu[3] * vx;
+  }
+};
 
 // mu_k = sum_i 36 a_i e_ki d_i for all 19 modes.
 template <class F>
-LBF_HD void forward_modes(const F d[Q], F mu[Q]) {
+LBF_HD void D3Q19::forward(const F d[Q], F mu[Q]) {
   // pair sums and differences: X, Y, Z axes; A=(1,1,0) B=(1,-1,0)
   // C=(1,0,1) D=(1,0,-1) E=(0,1,1) F=(0,1,-1) diagonals
   const F sX = d[1] + d[2], dX = d[1] - d[2];
@@ -91,7 +118,7 @@ LBF_HD void forward_modes(const F d[Q], F mu[Q]) {
 
 // d_i = sum_k e_ki nu_k for all 19 populations.
 template <class F>
-LBF_HD void back_transform(const F nu[Q], F d[Q]) {
+LBF_HD void D3Q19::back(const F nu[Q], F d[Q]) {
   // even parts
   const F J = nu[0] - F(2) * nu[16];
   const F M = nu[5] - nu[17];
@@ -131,5 +158,70 @@ LBF_HD void back_transform(const F nu[Q], F d[Q]) {
   d[15] = eE + oE; d[16] = eE - oE;
   d[17] = eF + oF; d[18] = eF - oF;
 }
+
+// ================================================================ D2Q9
+// Velocity order: 0 rest; 1..4 = +x -x +y -y; 5/6 = +-(1,1); 7/8 = +-(1,-1).
+// Modes (Table I): 0..2 conserved, 3 bulk, 4..5 shear, 6..7 odd kinetic,
+// 8 even kinetic.  Weights 4/9, 1/9, 1/36 (the three-speed solution of the
+// isotropy conditions of Sec. II, with c_s^2 = 1/3).
+struct D2Q9 {
+  static constexpr int Q = 9, D = 2;
+  static constexpr int NSTRESS = 3;
+  static constexpr int CX[Q] = {0, 1, -1, 0, 0, 1, -1, 1, -1};
+  static constexpr int CY[Q] = {0, 0, 0, 1, -1, 1, -1, -1, 1};
+  static constexpr int CZ[Q] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  static constexpr int OPP[Q] = {0, 2, 1, 4, 3, 6, 5, 8, 7};
+  static constexpr float A36[Q] = {16, 4, 4, 4, 4, 1, 1, 1, 1};
+  static constexpr float W36[Q] = {36, 12, 12, 144, 16, 4, 24, 24, 576};
+  static constexpr int CLS[Q] = {0, 0, 0, 1, 2, 2, 3, 3, 4};
+
+  // mu_k = sum_i 36 a_i e_ki d_i.  Pairs: X = (1, 2), Y = (3, 4),
+  // A = (1,1) (5, 6), B = (1,-1) (7, 8).
+  template <class F> static LBF_HD void forward(const F d[Q], F mu[Q]) {
+    const F sX = d[1] + d[2], dX = d[1] - d[2];
+    const F sY = d[3] + d[4], dY = d[3] - d[4];
+    const F sA = d[5] + d[6], dA = d[5] - d[6];
+    const F sB = d[7] + d[8], dB = d[7] - d[8];
+    const F r16 = F(16) * d[0];
+    const F Sax = sX + sY, Sd = sA + sB;
+    mu[0] = (r16 + F(4) * Sax) + Sd;                          // 1
+    mu[3] = F(4) * (Sax + Sd) - F(2) * r16;                   // 3c^2 - 2
+    mu[4] = F(4) * (sX - sY);                                 // 2cx^2 - c^2
+    mu[5] = sA - sB;                                          // cx cy
+    mu[8] = (F(2) * r16 - F(16) * Sax) + F(8) * Sd;           // 9c^4 - 15c^2 + 2
+    const F Px = dA + dB, Py = dA - dB;
+    mu[1] = F(4) * dX + Px;                                   // cx
+    mu[2] = F(4) * dY + Py;                                   // cy
+    mu[6] = F(2) * Px - F(4) * dX;                            // (3c^2 - 4) cx
+    mu[7] = F(2) * Py - F(4) * dY;                            // (3c^2 - 4) cy
+  }
+
+  // d_i = sum_k e_ki nu_k.
+  template <class F> static LBF_HD void back(const F nu[Q], F d[Q]) {
+    const F base = nu[0] + nu[3];                 // e_0 = e_3 = 1 on the axis velocities
+    const F eX = (base + nu[4]) - F(4) * nu[8];
+    const F eY = (base - nu[4]) - F(4) * nu[8];
+    const F g = (nu[0] + F(4) * nu[3]) + F(8) * nu[8];
+    const F eA = g + nu[5], eB = g - nu[5];
+    const F oX = nu[1] - nu[6];
+    const F oY = nu[2] - nu[7];
+    const F s1 = nu[1] + F(2) * nu[6], s2 = nu[2] + F(2) * nu[7];
+    const F oA = s1 + s2, oB = s1 - s2;
+    d[0] = (nu[0] - F(2) * nu[3]) + F(2) * nu[8];
+    d[1] = eX + oX; d[2] = eX - oX;
+    d[3] = eY + oY; d[4] = eY - oY;
+    d[5] = eA + oA; d[6] = eA - oA;
+    d[7] = eB + oB; d[8] = eB - oB;
+  }
+
+  // mu_3 = 3 |j|^2 / R, mu_4 = (jx^2 - jy^2) / R, mu_5 = jx jy / R
+  template <class F> static LBF_HD void stress_eq(const F mu[Q], F iR, F eq[NSTRESS]) {
+    const F vx = mu[1] * iR, vy = mu[2] * iR;
+    const F xx = mu[1] * vx, yy = mu[2] * vy;
+    eq[0] = F(3) * (xx + yy);
+    eq[1] = xx - yy;
+    eq[2] = mu[1] * vy;
+  }
+};
 
 }  // namespace lbf

@@ -17,7 +17,8 @@ STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
 STORAGE_DTYPE = {"f32": torch.float32, "f16": torch.float16, "bf16": torch.bfloat16}
 INIT = {"rest": 0, "thermal": 1, "fields": 2, "keep": 3}
 THERMAL_MODES = {"all": 0, "stress_only": 1}
-Q = 19
+LATTICE = {"d3q19": 0, "d2q9": 1}
+LATTICE_QD = {"d3q19": (19, 3), "d2q9": (9, 2)}  # populations q, dimension d
 
 
 class LbParams(ctypes.Structure):
@@ -28,7 +29,7 @@ class LbParams(ctypes.Structure):
         ("gamma_bulk", ctypes.c_double), ("gamma_shear", ctypes.c_double),
         ("gamma_odd", ctypes.c_double), ("gamma_even", ctypes.c_double),
         ("seed", ctypes.c_uint64),
-        ("thermal_modes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("thermal_modes", ctypes.c_int32), ("lattice", ctypes.c_int32),
     ]
 
 
@@ -112,16 +113,17 @@ def _check(rc, where):
 
 
 def make_params(nx, ny, nz, storage="f32", rho0=1.0, kT=0.0, gamma_bulk=0.5, gamma_shear=0.5,
-                gamma_odd=0.0, gamma_even=0.0, seed=0, thermal_modes="all"):
+                gamma_odd=0.0, gamma_even=0.0, seed=0, thermal_modes="all", lattice="d3q19"):
     return LbParams(int(nx), int(ny), int(nz), STORAGE[storage], float(rho0), float(kT),
                     float(gamma_bulk), float(gamma_shear), float(gamma_odd), float(gamma_even),
-                    int(seed), THERMAL_MODES[thermal_modes], 0)
+                    int(seed), THERMAL_MODES[thermal_modes], LATTICE[lattice])
 
 
-def physical_params(b, h, rho, eta, zeta, kBT):
+def physical_params(b, h, rho, eta, zeta, kBT, lattice="d3q19"):
     """Lattice rho0, kT, gamma_shear, gamma_bulk from physical spacing, time
-    step, density, viscosities and k_B T (Sec. VI), via the C ABI."""
-    p = make_params(1, 1, 1)
+    step, density, viscosities and k_B T (Sec. VI), via the C ABI; the
+    lattice fixes the dimension d."""
+    p = make_params(1, 1, 1, lattice=lattice)
     _check(lib().lb_params_from_physical(b, h, rho, eta, zeta, kBT, ctypes.byref(p)),
            "lb_params_from_physical")
     return dict(rho0=p.rho0, kT=p.kT, gamma_shear=p.gamma_shear, gamma_bulk=p.gamma_bulk)
@@ -144,18 +146,27 @@ class _Gathers:
     def _dims(self):
         return self.nz, self.ny, self.nx
 
+    @property
+    def q(self):
+        return LATTICE_QD[self.lattice][0]
+
+    @property
+    def dim(self):
+        return LATTICE_QD[self.lattice][1]
+
     def populations(self):
-        out = torch.empty((Q, *self._dims()), dtype=torch.float32, device=self.device)
+        out = torch.empty((self.q, *self._dims()), dtype=torch.float32, device=self.device)
         _check(lib().lb_populations(self._ctx, _aligned(out)), "lb_populations")
         return out
 
     def moments(self):
-        out = torch.empty((4, *self._dims()), dtype=torch.float32, device=self.device)
+        """(1 + d, nz, ny, nx): rho, jx, jy[, jz]."""
+        out = torch.empty((1 + self.dim, *self._dims()), dtype=torch.float32, device=self.device)
         _check(lib().lb_moments(self._ctx, _aligned(out)), "lb_moments")
         return out
 
     def modes(self):
-        out = torch.empty((Q, *self._dims()), dtype=torch.float32, device=self.device)
+        out = torch.empty((self.q, *self._dims()), dtype=torch.float32, device=self.device)
         _check(lib().lb_modes(self._ctx, _aligned(out)), "lb_modes")
         return out
 
@@ -174,33 +185,37 @@ class _Gathers:
 
 
 class Lattice(_Gathers):
-    """One periodic D3Q19 lattice; the state is a caller-owned torch tensor
-    (19, nz, ny, nx) of scaled deviations in the storage dtype."""
+    """One periodic lattice (D3Q19, or D2Q9 with nz = 1); the state is a
+    caller-owned torch tensor (q, nz, ny, nx) of scaled deviations in the
+    storage dtype."""
 
     def __init__(self, nx, ny, nz, storage="f32", rho0=1.0, kT=0.0, gamma_bulk=0.5,
                  gamma_shear=0.5, gamma_odd=0.0, gamma_even=0.0, seed=0, thermal_modes="all",
-                 init="rest", fields=None, t0=0, device="cuda", stream=None, state=None):
+                 init="rest", fields=None, t0=0, device="cuda", stream=None, state=None,
+                 lattice="d3q19"):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.storage = storage
+        self.lattice = lattice
         self.params = make_params(nx, ny, nz, storage, rho0, kT, gamma_bulk, gamma_shear,
-                                  gamma_odd, gamma_even, seed, thermal_modes)
+                                  gamma_odd, gamma_even, seed, thermal_modes, lattice)
         self.device = torch.device(device)
         nbytes = lib().lb_state_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             raise LBError(LB_EINVAL, "lb_state_bytes")
-        shape = (Q, self.nz, self.ny, self.nx)
+        shape = (self.q, self.nz, self.ny, self.nx)
         if state is None:
             state = torch.empty(shape, dtype=STORAGE_DTYPE[storage], device=self.device)
         if tuple(state.shape) != shape or state.dtype != STORAGE_DTYPE[storage] or not state.is_contiguous():
-            raise ValueError("state must be a contiguous (19, nz, ny, nx) tensor of the storage dtype")
+            raise ValueError("state must be a contiguous (q, nz, ny, nx) tensor of the storage dtype")
         self.state = state
         f = None
         if init == "fields":
+            fshape = (1 + self.dim, self.nz, self.ny, self.nx)
             if fields is None:
-                raise ValueError("init='fields' needs fields (4, nz, ny, nx)")
+                raise ValueError(f"init='fields' needs fields {fshape}")
             self._fields = fields.to(device=self.device, dtype=torch.float32).contiguous()
-            if tuple(self._fields.shape) != (4, self.nz, self.ny, self.nx):
-                raise ValueError("fields must be (4, nz, ny, nx)")
+            if tuple(self._fields.shape) != fshape:
+                raise ValueError(f"fields must be {fshape}")
             f = _aligned(self._fields)
         sp, self.stream = _stream_ptr(self.device, stream)
         ctx = ctypes.c_void_p()
@@ -243,6 +258,7 @@ class ReplicaView(_Gathers):
     def __init__(self, ens, r, ctx):
         p = ens.params[r]
         self.nx, self.ny, self.nz = p.nx, p.ny, p.nz
+        self.lattice = ens.lattice
         self.device = ens.device
         self._ctx = ctx
         self._ens = ens
@@ -260,13 +276,16 @@ class ReplicaView(_Gathers):
 
 
 class Ensemble:
-    """Independent replicas (own box, rates, kT, seed; one storage type)
-    advanced together, one kernel launch per step for all of them."""
+    """Independent replicas (own box, rates, kT, seed; one storage type and
+    one lattice) advanced together, one kernel launch per step for all of
+    them."""
 
-    def __init__(self, replicas, storage="f32", init="thermal", t0=0, device="cuda", stream=None):
+    def __init__(self, replicas, storage="f32", init="thermal", t0=0, device="cuda", stream=None,
+                 lattice="d3q19"):
         self.storage = storage
+        self.lattice = lattice
         self.device = torch.device(device)
-        self.params = [make_params(storage=storage, **r) for r in replicas]
+        self.params = [make_params(storage=storage, lattice=lattice, **r) for r in replicas]
         n = len(self.params)
         self._arr = (LbParams * n)(*self.params)
         nbytes = lib().lb_batch_pool_bytes(self._arr, n)
@@ -305,7 +324,8 @@ class Ensemble:
         p = self.params[r]
         off = lib().lb_batch_offset(self._arr, len(self.params), int(r))
         nbytes = lib().lb_state_bytes(ctypes.byref(p))
-        return self.pool[off:off + nbytes].view(STORAGE_DTYPE[self.storage]).view(Q, p.nz, p.ny, p.nx)
+        q = LATTICE_QD[self.lattice][0]
+        return self.pool[off:off + nbytes].view(STORAGE_DTYPE[self.storage]).view(q, p.nz, p.ny, p.nx)
 
     def schedule(self):
         s = LbSchedule()

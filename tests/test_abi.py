@@ -40,12 +40,24 @@ def test_state_bytes():
         assert L.lb_state_bytes(ctypes.byref(p)) == 19 * 5 * 7 * 3 * size
     p = lb.make_params(512, 512, 512)
     assert L.lb_state_bytes(ctypes.byref(p)) == 19 * 512 ** 3 * 4
+    for storage, size in (("f32", 4), ("bf16", 2)):
+        p = lb.make_params(6, 5, 1, storage=storage, lattice="d2q9")
+        assert L.lb_state_bytes(ctypes.byref(p)) == 9 * 6 * 5 * size
+
+
+def test_d2q9_needs_a_flat_box():
+    L = lb.lib()
+    p = lb.make_params(8, 8, 2, lattice="d2q9")
+    assert L.lb_state_bytes(ctypes.byref(p)) == 0
+    ctx = ctypes.c_void_p()
+    assert L.lb_init(ctypes.byref(p), ctypes.c_void_p(256), None, 0, None, 0, ctypes.byref(ctx)) == lb.LB_EINVAL
+    assert "nz = 1" in L.lb_last_error().decode()
 
 
 @pytest.mark.parametrize("field,value", [
     ("nx", 0), ("ny", -3), ("storage", 7), ("rho0", 0.0), ("rho0", float("nan")), ("kT", -1e-4),
     ("gamma_bulk", 1.5), ("gamma_shear", -1.01), ("gamma_odd", float("inf")), ("thermal_modes", 5),
-    ("reserved", 1)])
+    ("lattice", 2), ("lattice", -1)])
 def test_invalid_params_rejected_without_device(field, value):
     L = lb.lib()
     p = lb.make_params(4, 4, 4)
@@ -97,6 +109,9 @@ def test_batch_pool_layout_and_validation():
     assert L.lb_batch_init(mixed, 2, ctypes.c_void_p(256), None, 1, 0, ctypes.byref(ctx)) == lb.LB_EINVAL
     assert L.lb_batch_init(arr, 3, ctypes.c_void_p(256), None, 2, 0, ctypes.byref(ctx)) == lb.LB_EUNSUPPORTED
     assert L.lb_batch_init(arr, 0, ctypes.c_void_p(256), None, 1, 0, ctypes.byref(ctx)) == lb.LB_EINVAL
+    two = (lb.LbParams * 2)(lb.make_params(3, 3, 1), lb.make_params(3, 3, 1, lattice="d2q9"))
+    assert L.lb_batch_init(two, 2, ctypes.c_void_p(256), None, 1, 0, ctypes.byref(ctx)) == lb.LB_EINVAL
+    assert "same lattice" in L.lb_last_error().decode()
 
 
 def test_strerror():

@@ -63,3 +63,28 @@ def test_invalid_physical_parameters(bad):
                                            args["kBT"], ctypes.byref(p))
     assert rc == lb.LB_EINVAL
     assert p.kT == 7.0
+
+
+def test_two_dimensional_mapping():
+    """D2Q9 (d = 2): rho is a mass per area, mu = k_B T h^2 / (c_s_hat^2 b^4),
+    zeta of Eq. bulkviscosity carries 1/d = 1/2; the mapped shear and sound
+    waves of the D2Q9 linear operator decay at the physical viscosities."""
+    case = dict(b=1e-9, h=2e-13, rho=1e-6, eta=8.9e-13, zeta=2.5e-12, kBT=1.380649e-23 * 300)
+    q = lb.physical_params(**case, lattice="d2q9")
+    b, h, rho = case["b"], case["h"], case["rho"]
+    assert th.nu_closed_form(q["gamma_shear"]) * b * b / h == pytest.approx(case["eta"] / rho, rel=1e-12)
+    assert th.zeta_closed_form(q["gamma_bulk"], d=2) * b * b / h == pytest.approx(case["zeta"] / rho, rel=1e-12)
+    cs2 = (1.0 / 3.0) * b * b / (h * h)
+    assert 3.0 * q["kT"] == pytest.approx(case["kBT"] / (rho * cs2 * b ** 2), rel=1e-12)
+    # the 3D mapping of the same numbers differs (d enters gamma_bulk and mu)
+    q3 = lb.physical_params(**case)
+    assert q3["gamma_bulk"] != pytest.approx(q["gamma_bulk"]) and q3["kT"] != pytest.approx(q["kT"])
+    c, a, e, w = oracle.tables(oracle.D2Q9)
+    g = th.mode_gammas(q["gamma_bulk"], q["gamma_shear"], 0, 0, q=9)
+    L = 1024
+    k = 2 * np.pi / L
+    nu_lat = -np.log(abs(th.shear_eigenvalue(L, 1, g, c, a, e, w, axis=1))) / k ** 2
+    assert nu_lat * b * b / h == pytest.approx(case["eta"] / rho, rel=1e-3)
+    att = -np.log(abs(th.sound_eigenvalue(L, 1, g, c, a, e, w, axis=1))) / k ** 2
+    want = 0.5 * (case["eta"] + case["zeta"]) / rho  # (2 eta (1 - 1/d) + zeta) / (2 rho) at d = 2
+    assert att * b * b / h == pytest.approx(want, rel=3e-3)

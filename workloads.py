@@ -25,6 +25,20 @@ LARGE_STEPS = 200
 # 768^3 16-bit storage case.
 XLARGE = dict(BASE, nx=768, ny=768, nz=768, kT=1e-4, gamma_shear=0.8, seed=1234)
 
+# D2Q9 (Table I) cases: a small trajectory case and a throughput case of
+# 2^28 sites (9.66 GB of fp32 state, about the size of the 512^3 D3Q19 one).
+SMALL_2D = dict(BASE, nx=64, ny=48, nz=1, kT=1e-4, gamma_shear=0.5, seed=1234, lattice="d2q9")
+LARGE_2D = dict(BASE, nx=16384, ny=16384, nz=1, kT=1e-4, gamma_shear=0.8, seed=1234, lattice="d2q9")
+
+
+def shear_wave_fields_2d(nx, ny, amplitude, periods=1, rho0=1.0):
+    """(3, 1, ny, nx) float32: rho = rho0, u_x(y) = U sin(2 pi n y / ny)."""
+    f = np.zeros((3, 1, ny, nx), dtype=np.float32)
+    f[0] = rho0
+    y = np.arange(ny)
+    f[1] = (amplitude * np.sin(2 * np.pi * periods * y / ny)).astype(np.float32)[None, :, None]
+    return f
+
 
 def shear_wave_fields(nx, ny, nz, amplitude, periods=1, rho0=1.0):
     """(4, nz, ny, nx) float32: rho = rho0, u_x(z) = U sin(2 pi n z / nz)."""
@@ -43,12 +57,12 @@ def density_wave_fields(nx, ny, nz, amplitude, periods=1, rho0=1.0):
     return f
 
 
-def random_fields(nx, ny, nz, seed, drho=0.05, du=0.03, rho0=1.0):
-    """(4, nz, ny, nx) float32 smooth-free random density and velocity."""
+def random_fields(nx, ny, nz, seed, drho=0.05, du=0.03, rho0=1.0, dim=3):
+    """(1 + dim, nz, ny, nx) float32 smooth-free random density and velocity."""
     rng = np.random.default_rng(seed)
-    f = np.empty((4, nz, ny, nx), dtype=np.float32)
+    f = np.empty((1 + dim, nz, ny, nx), dtype=np.float32)
     f[0] = rho0 * (1 + rng.uniform(-drho, drho, (nz, ny, nx)))
-    f[1:] = rng.uniform(-du, du, (3, nz, ny, nx))
+    f[1:] = rng.uniform(-du, du, (dim, nz, ny, nx))
     return f
 
 
