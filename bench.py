@@ -5,8 +5,9 @@ Workload: a 512^3 periodic box, fp32 deviation storage updated in place (AA
 pattern, one buffer of 10.2 GB), rho0 = 1, kT = 1e-4, gamma_shear = 0.8,
 gamma_bulk = 0.5, kinetic rates 0, thermal (random seeded rest) start with
 Philox seed 1234.  One step = the whole fused collide-and-stream update of
-every site.  The same box is also timed with fp16 and bf16 storage, and the
-96-replica ensemble in one launch per step.
+every site.  The same box is also timed with fp16 and bf16 storage, the
+96-replica ensemble in one launch per step, and the D2Q9 lattice (Table I)
+on a 16384^2 box (2^28 sites) with fp32 and bf16 storage.
 
 Prints one JSON line.  `value` is MLUPS (million lattice-site updates per
 second) of the fp32 run with the state resident in HBM; `roofline` compares
@@ -28,6 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 W36 = [36, 12, 12, 12, 24, 48, 16, 4, 4, 4, 24, 24, 24, 8, 8, 8, 72, 48, 16]  # 36 w_k, Table II
+W36_D2Q9 = [36, 12, 12, 144, 16, 4, 24, 24, 576]  # 36 w_k, Table I
 KERNEL_SOURCES = ["paper_0707_1581_amd/csrc/lbf_kernels.h", "paper_0707_1581_amd/csrc/lbf_math.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_aa_step_512.json")
 
@@ -66,47 +68,68 @@ def time_steps(step, steps, warmup, sync_stream):
     return e0.elapsed_time(e1) / steps  # ms per step
 
 
-def mode_variance_dev(lat, rho0, kT):
-    """max_k |var(m_k - m_k^eq) / (mu rho_mean w_k) - 1| of the current state
+def stress_eq(lattice, k, j, rho):
+    """Equilibrium value m_k^eq of stress mode k from j and rho (the stress
+    of the equilibrium distribution projected on Table II / Table I), or
+    None for a mode without one."""
+    if lattice == "d2q9":
+        jx, jy = j[0], j[1]
+        f = {3: lambda: 3 * (jx * jx + jy * jy), 4: lambda: jx * jx - jy * jy, 5: lambda: jx * jy}
+    else:
+        jx, jy, jz = j[0], j[1], j[2]
+        f = {4: lambda: jx * jx + jy * jy + jz * jz, 5: lambda: 2 * jx * jx - jy * jy - jz * jz,
+             6: lambda: jy * jy - jz * jz, 7: lambda: jx * jy, 8: lambda: jy * jz, 9: lambda: jz * jx}
+    return f[k]() / rho if k in f else None
+
+
+def mode_ratios(lat, rho0, kT, lattice="d3q19"):
+    """Per-mode var(m_k - m_k^eq) / (mu rho_mean w_k) of the current state
     (conserved modes about their lattice mean)."""
     import torch
+    w36 = W36_D2Q9 if lattice == "d2q9" else W36
+    d = 2 if lattice == "d2q9" else 3
     m = lat.modes()
     mu = 3.0 * kT
     rho = rho0 + m[0].double()
     rbar = float(rho.mean())
-    j = m[1:4].double()
-    worst = 0.0
-    for k in range(19):
+    j = m[1:1 + d].double()
+    out = []
+    for k in range(len(w36)):
         x = m[k].double()
-        if 4 <= k <= 9:
-            jx, jy, jz = j[0], j[1], j[2]
-            eq = {4: jx * jx + jy * jy + jz * jz, 5: 2 * jx * jx - jy * jy - jz * jz,
-                  6: jy * jy - jz * jz, 7: jx * jy, 8: jy * jz, 9: jz * jx}[k] / rho
+        eq = stress_eq(lattice, k, j, rho)
+        if eq is not None:
             x = x - eq
-        var = float(((x - x.mean()) ** 2).mean()) if k < 4 else float((x ** 2).mean() - x.mean() ** 2)
-        worst = max(worst, abs(var / (mu * rbar * W36[k] / 36.0) - 1.0))
+            del eq
+        var = float((x * x).mean() - x.mean() ** 2)
+        out.append(var / (mu * rbar * w36[k] / 36.0))
         del x
     del m, rho, j
     torch.cuda.empty_cache()
-    return worst
+    return out
 
 
-def run_lattice(box, storage, steps, warmup, cfg, check=True, tune=True):
+def mode_variance_dev(lat, rho0, kT, lattice="d3q19"):
+    """max_k |var(m_k - m_k^eq) / (mu rho_mean w_k) - 1| of the current state."""
+    return max(abs(r - 1.0) for r in mode_ratios(lat, rho0, kT, lattice))
+
+
+def run_lattice(dims, storage, steps, warmup, cfg, check=True, tune=True, lattice="d3q19"):
     import torch
     import paper_0707_1581_amd as lbf
-    lat = lbf.Lattice(box, box, box, storage=storage, init="thermal", **cfg)
-    sites = box ** 3
+    nx, ny, nz = dims
+    lat = lbf.Lattice(nx, ny, nz, storage=storage, init="thermal", lattice=lattice, **cfg)
+    sites = nx * ny * nz
     if tune:  # on a scratch copy of the state, outside the timed region
         lat.autotune(steps=10)
     ms = time_steps(lat.step, steps, warmup, lat.stream)
     bpe = 4 if storage == "f32" else 2
-    alg = 2 * 19 * bpe * sites  # algorithmic bytes per step launch
+    alg = 2 * lat.q * bpe * sites  # algorithmic bytes per step launch
     out = dict(storage=storage, ms_per_step=ms, mlups=sites / ms / 1e3,
                achieved_gbs=alg / ms / 1e6, alg_bytes_per_launch=alg, schedule=lat.schedule())
     if check:
         nb, sums = lat.check()
         out["bad_sites"] = nb
-        out["mode_variance_max_dev"] = mode_variance_dev(lat, cfg["rho0"], cfg["kT"])
+        out["mode_variance_max_dev"] = mode_variance_dev(lat, cfg["rho0"], cfg["kT"], lattice)
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -151,29 +174,6 @@ def cpu_baseline(budget_s=15.0):
             "kind": "oracle",
             "sample": f"128^3 box, thermal start, kT=1e-4, gamma_shear=0.8, {k} steps after 1 warm-up "
                       f"step, FP64 two-buffer push, {dt:.1f} s"}
-
-
-def mode_ratios(lat, rho0, kT):
-    """Per-mode var(m_k - m_k^eq) / (mu rho_mean w_k) of the current state."""
-    import torch
-    m = lat.modes()
-    mu = 3.0 * kT
-    rho = rho0 + m[0].double()
-    rbar = float(rho.mean())
-    out = []
-    for k in range(19):
-        x = m[k].double()
-        if 4 <= k <= 9:
-            jx, jy, jz = m[1].double(), m[2].double(), m[3].double()
-            x = x - {4: jx * jx + jy * jy + jz * jz, 5: 2 * jx * jx - jy * jy - jz * jz,
-                     6: jy * jy - jz * jz, 7: jx * jy, 8: jy * jz, 9: jz * jx}[k] / rho
-            del jx, jy, jz
-        var = float((x * x).mean() - x.mean() ** 2)
-        out.append(var / (mu * rbar * W36[k] / 36.0))
-        del x
-    del m, rho
-    torch.cuda.empty_cache()
-    return out
 
 
 def wave_amplitude(lat, q):
@@ -308,16 +308,25 @@ def main():
     import workloads
     cfg = {k: workloads.LARGE[k] for k in ("rho0", "kT", "gamma_bulk", "gamma_shear", "gamma_odd",
                                           "gamma_even", "seed")}
-    main_run = run_lattice(args.box, "f32", args.steps, args.warmup, cfg, tune=not args.no_tune)
+    box3 = (args.box, args.box, args.box)
+    main_run = run_lattice(box3, "f32", args.steps, args.warmup, cfg, tune=not args.no_tune)
     variants = {}
     if not args.no_variants:
         for st in ("f16", "bf16"):
-            r = run_lattice(args.box, st, args.steps, args.warmup, cfg, tune=not args.no_tune)
+            r = run_lattice(box3, st, args.steps, args.warmup, cfg, tune=not args.no_tune)
             r["roofline_frac"] = r["achieved_gbs"] / HBM_PEAK_GBS
             r["gain_over_f32"] = r["mlups"] / main_run["mlups"]
             variants[st] = r
         for st in ("f32", "f16"):
             variants[f"ensemble96_{st}"] = run_ensemble(st, args.ensemble_steps, args.warmup)
+        c2 = workloads.LARGE_2D
+        cfg2 = {k: c2[k] for k in cfg}
+        for st in ("f32", "bf16"):
+            r = run_lattice((c2["nx"], c2["ny"], 1), st, args.steps, args.warmup, cfg2, tune=not args.no_tune,
+                            lattice="d2q9")
+            r["roofline_frac"] = r["achieved_gbs"] / HBM_PEAK_GBS
+            r["workload"] = "D2Q9, 16384^2 periodic box, same parameters and start as the 3D box"
+            variants[f"d2q9_{st}"] = r
     if args.copy_calibration:
         copy_calibration()
 
