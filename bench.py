@@ -153,16 +153,29 @@ def run_ensemble(storage, steps, warmup):
     return out
 
 
-def cpu_baseline(budget_s=15.0):
-    """The FP64 oracle on the host cores: a 128^3 box from a thermal start,
-    as many steps as fit in the budget (at least one)."""
+def host_info():
+    """CPU model, logical CPU count and RAM of the host (from /proc)."""
+    model, ram = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "ram_gib": ram}
+
+
+def _oracle_mlups(p, sites, budget_s, threads):
     import oracle
-    import workloads
-    cfg = dict(workloads.MID, kT=1e-4, gamma_shear=0.8)
-    p = oracle.params(**{k: cfg[k] for k in ("nx", "ny", "nz", "rho0", "kT", "gamma_bulk",
-                                             "gamma_shear", "gamma_odd", "gamma_even", "seed")})
+    oracle.set_num_threads(threads)
     n = oracle.init(p, oracle.INIT_THERMAL)
-    sites = cfg["nx"] * cfg["ny"] * cfg["nz"]
     t0 = time.perf_counter()
     n = oracle.run(p, n, 0, 1)
     one = time.perf_counter() - t0
@@ -170,10 +183,28 @@ def cpu_baseline(budget_s=15.0):
     t0 = time.perf_counter()
     n = oracle.run(p, n, 1, k)
     dt = time.perf_counter() - t0
-    return {"value": sites * k / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
+    return sites * k / dt / 1e6, k, dt
+
+
+def cpu_baseline(budget_s=12.0, single_budget_s=4.0):
+    """The FP64 oracle on the host cores: a 128^3 box from a thermal start,
+    as many steps as fit in the budget (at least one), with all OpenMP
+    threads; and a 64^3 box on one thread."""
+    import oracle
+    import workloads
+    keys = ("nx", "ny", "nz", "rho0", "kT", "gamma_bulk", "gamma_shear", "gamma_odd", "gamma_even", "seed")
+    cfg = dict(workloads.MID, kT=1e-4, gamma_shear=0.8)
+    nthreads = oracle.num_threads()
+    v, k, dt = _oracle_mlups(oracle.params(**{q: cfg[q] for q in keys}), 128 ** 3, budget_s, nthreads)
+    c1 = dict(cfg, nx=64, ny=64, nz=64)
+    v1, k1, dt1 = _oracle_mlups(oracle.params(**{q: c1[q] for q in keys}), 64 ** 3, single_budget_s, 1)
+    oracle.set_num_threads(nthreads)
+    return {"value": v, "unit": "MLUPS", "cores": nthreads, "kind": "oracle",
             "sample": f"128^3 box, thermal start, kT=1e-4, gamma_shear=0.8, {k} steps after 1 warm-up "
-                      f"step, FP64 two-buffer push, {dt:.1f} s"}
+                      f"step, FP64 two-buffer push, {dt:.1f} s",
+            "single_thread": {"value": v1, "unit": "MLUPS",
+                              "sample": f"64^3 box, same parameters, {k1} steps on 1 thread, {dt1:.1f} s"},
+            "host": host_info()}
 
 
 def wave_amplitude(lat, q):
