@@ -155,3 +155,27 @@ def test_checkpoint_resume_bit_identical():
     resumed = lbf.Lattice(**cfg, init="keep", state=snap, t0=t)
     resumed.step(17)
     assert torch.equal(resumed.state, full.state)
+
+
+@pytest.mark.parametrize("gammas", [(1.0, 1.0, 1.0, 1.0), (-1.0, -1.0, -1.0, -1.0), (1.0, -1.0, 0.0, 1.0),
+                                    (0.0, 0.0, 0.0, 0.0)])
+def test_extreme_rates(gammas):
+    """|gamma| = 1 makes every noise amplitude sqrt(1 - gamma^2) zero (gamma = 1:
+    no relaxation, pure streaming of a thermal state; gamma = -1: reflection
+    about equilibrium); gamma = 0 relaxes fully in one step."""
+    gb, gs, go, ge = gammas
+    cfg = dict(nx=7, ny=6, nz=5, rho0=1.0, kT=1e-3, gamma_bulk=gb, gamma_shear=gs, gamma_odd=go,
+               gamma_even=ge, seed=77)
+    for t, err in run_pair(cfg, "thermal", [1, 2, 9]):
+        assert err < TOL, (gammas, t, err)
+
+
+def test_zero_steps_is_a_no_op():
+    cfg = dict(nx=9, ny=4, nz=3, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.5, gamma_odd=0.0,
+               gamma_even=0.0, seed=5)
+    lat = lbf.Lattice(**cfg, init="thermal")
+    lat.step(3)
+    before = lat.state.clone()
+    lat.step(0)
+    assert lat.t == 3
+    assert torch.equal(lat.state, before)
