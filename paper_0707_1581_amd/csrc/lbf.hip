@@ -69,6 +69,9 @@ void div_magic(uint32_t d, uint32_t& m, uint32_t& s1, uint32_t& s2) {
 // per-mode coefficients of the model's collision (rates by mode class).
 template <class M>
 LatDesc make_desc_m(const lb_params& p, uint64_t base) {
+  static_assert(M::Q <= (int)(sizeof(LatDesc::ci) / sizeof(float)), "ci too small for this model");
+  static_assert(M::Q - M::D - 1 <= (int)(sizeof(LatDesc::ca) / sizeof(float)), "ca/cc too small for this model");
+  static_assert(M::NSTRESS <= (int)(sizeof(LatDesc::cb) / sizeof(float)), "cb too small for this model");
   LatDesc L;
   std::memset(&L, 0, sizeof(L));
   L.base = base;
