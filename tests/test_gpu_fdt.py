@@ -118,7 +118,7 @@ def test_transverse_momentum_correlation_d2q9():
     C(tau) of the transverse momentum modes follows the D2Q9 linearised
     operator, and C(0) = N rho0 kT.  A 32 x 32 lattice has only two
     transverse modes at the smallest wave vector, so the run is longer than
-    the 3D one and C(0) is judged by its own standard error."""
+    the 3D one and C(0) is checked against its own standard error."""
     L, kT, gs, gb = 32, 1e-4, 0.5, 0.5
     mu = 3 * kT
     cfg = dict(nx=L, ny=L, nz=1, rho0=1.0, kT=kT, gamma_bulk=gb, gamma_shear=gs, gamma_odd=0.0,
