@@ -32,6 +32,9 @@ W36 = [36, 12, 12, 12, 24, 48, 16, 4, 4, 4, 24, 24, 24, 8, 8, 8, 72, 48, 16]  # 
 W36_D2Q9 = [36, 12, 12, 144, 16, 4, 24, 24, 576]  # 36 w_k, Table I
 KERNEL_SOURCES = ["paper_0707_1581_amd/csrc/lbf_kernels.h", "paper_0707_1581_amd/csrc/lbf_math.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_aa_step_512.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_step.json")
+# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (fp32 vector 157.3 TFLOP/s = 2 x 2 x this)
+VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 
 
 def kernel_hash():
@@ -53,6 +56,24 @@ def stored_traffic(storage):
     if rec.get("kernel_hash") != kernel_hash():
         return None
     return rec.get("bytes_per_launch", {}).get(storage)
+
+
+def stored_valu(key, mlups):
+    """VALU figure of a run: instructions per site-update from the SQ_INSTS_VALU
+    counter (stored with the kernel-source hash; mean of the default
+    schedule's even and odd kernels) times the measured site-update rate,
+    against the VALU issue peak."""
+    try:
+        with open(VALU_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash() or key not in rec.get("valu_instr_per_site", {}):
+        return None
+    ips = rec["valu_instr_per_site"][key]
+    achieved = ips * mlups * 1e6
+    return {"bound": "alu", "instr_per_site": ips, "achieved": achieved, "peak": VALU_PEAK_LANE_INSTR,
+            "unit": "lane-instructions/s", "frac": achieved / VALU_PEAK_LANE_INSTR}
 
 
 def time_steps(step, steps, warmup, sync_stream):
@@ -126,6 +147,7 @@ def run_lattice(dims, storage, steps, warmup, cfg, check=True, tune=True, lattic
     alg = 2 * lat.q * bpe * sites  # algorithmic bytes per step launch
     out = dict(storage=storage, ms_per_step=ms, mlups=sites / ms / 1e3,
                achieved_gbs=alg / ms / 1e6, alg_bytes_per_launch=alg, schedule=lat.schedule())
+    out["valu"] = stored_valu(f"{lattice}_{storage}", out["mlups"])
     if check:
         nb, sums = lat.check()
         out["bad_sites"] = nb
