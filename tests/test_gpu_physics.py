@@ -182,3 +182,46 @@ def test_stress_only_noise_underthermalises_kinetic_modes():
     say(f"kinetic-mode variance ratios: all {res['all'][10:].round(3)}, stress-only {res['stress_only'][10:].round(3)}")
     assert np.all(np.abs(res["all"] - 1) < 0.02)
     assert np.all(res["stress_only"][10:] < 0.9)
+
+
+@pytest.mark.parametrize("gb,gs", [(0.3, 0.5), (0.8, 0.0)])
+def test_sound_wave_follows_linear_operator(gb, gs):
+    """kT = 0 standing density wave rho = rho0 (1 + A sin(q z)) on 8 x 8 x 128:
+    the GPU's density profile equals the exact FP64 1 x 1 x 128 reduction, and
+    its Fourier amplitude follows the linearised one-step operator, whose
+    q -> 0 limit is the sound speed c_s and the attenuation (4 nu / 3 +
+    zeta / rho) / 2 of Eqs. shearviscosity and bulkviscosity."""
+    A, L = 1e-4, 128
+    cfg = dict(nx=8, ny=8, nz=L, rho0=1.0, kT=0.0, gamma_bulk=gb, gamma_shear=gs, gamma_odd=0.0,
+               gamma_even=0.0, seed=0)
+    q = 2 * np.pi / L
+    f = workloads.density_wave_fields(8, 8, L, A)
+    lat = lbf.Lattice(**cfg, init="fields", fields=torch.from_numpy(f))
+    p = oracle_params(dict(cfg, nx=1, ny=1))
+    n0 = oracle.init(p, oracle.INIT_FIELDS, workloads.density_wave_fields(1, 1, L, A).astype(np.float64))
+    c, a, e, w = oracle.tables()
+    z = np.arange(L)
+    ph = np.exp(-1j * q * z)
+    f0 = (n0[:, :, 0, 0] * ph[None, :]).sum(axis=1)
+    Lop = th.one_step_operator([0, 0, q], th.mode_gammas(gb, gs, 0, 0), c, a, e, w)
+    n, t = n0, 0
+    for target in (1, 2, 100, 300, 600):
+        lat.step(target - t)
+        n = oracle.run(p, n, t, target - t)
+        t = target
+        # rho - rho0 from the modes gather (m_0), which keeps the deviation's precision
+        drho = lat.modes()[0].double()
+        prof = drho.mean(dim=(1, 2)).cpu().numpy()
+        assert float((drho - drho.mean(dim=(1, 2))[:, None, None]).abs().max()) < 1e-12
+        want = oracle.moments(p, n)[0, :, 0, 0] - cfg["rho0"]
+        assert np.abs(prof - want).max() < 1e-4 * A, (t, np.abs(prof - want).max())
+        rq = (prof * ph).sum()
+        pred = (np.linalg.matrix_power(Lop, t) @ f0).sum()
+        assert abs(rq - pred) < 1e-3 * abs(f0.sum()), (t, rq, pred)
+    lat.close()
+    lam = th.sound_eigenvalue(L, 1, th.mode_gammas(gb, gs, 0, 0), c, a, e, w)
+    att = -np.log(abs(lam)) / q ** 2
+    want_att = 0.5 * (4.0 / 3.0 * th.nu_closed_form(gs) + th.zeta_closed_form(gb))
+    say(f"sound gb={gb} gs={gs}: attenuation {att:.5f} vs closed form {want_att:.5f}, "
+        f"speed {abs(np.angle(lam)) / q:.5f} vs {np.sqrt(1 / 3):.5f}")
+    assert att == pytest.approx(want_att, rel=0.02)

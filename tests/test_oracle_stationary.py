@@ -62,6 +62,7 @@ def test_mode_variances_and_structure_factor(gs, gb, go, ge):
         assert abs(r - 1) < max(5 * se, 0.003) and abs(r - 1) < 0.02, (k, r, se)
     # flat structure factor S(q) = mu rho0 for q != 0, radially binned
     S = np.mean(sq, axis=0) / (mu * rho0)
+    assert S[0, 0, 0] < 1e-20  # S(0) = 0: total mass is exactly conserved
     k = np.fft.fftfreq(L) * L
     kk = np.sqrt(k[:, None, None] ** 2 + k[None, :, None] ** 2 + k[None, None, :] ** 2)
     for lo, hi in [(0.5, 3), (3, 6), (6, 9), (9, 15)]:
