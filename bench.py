@@ -158,6 +158,19 @@ def run_lattice(dims, storage, steps, warmup, cfg, check=True, tune=True, lattic
     return out
 
 
+def ensemble_mode_variances(ens, reps):
+    """Per-replica var(m_k - m_k^eq) / (mu_r rho_mean w_k) of the final state
+    of every replica (each with its own kT), and their site-weighted pool:
+    the pooled ratio has a standard error of about sqrt(2 / total sites)."""
+    ratios, weights = [], []
+    for r, rp in enumerate(reps):
+        ratios.append(mode_ratios(ens.view(r), rp["rho0"], rp["kT"]))
+        weights.append(rp["nx"] * rp["ny"] * rp["nz"])
+    W = float(sum(weights))
+    pooled = [sum(w * rr[k] for w, rr in zip(weights, ratios)) / W for k in range(len(ratios[0]))]
+    return pooled, ratios
+
+
 def run_ensemble(storage, steps, warmup):
     import torch
     import paper_0707_1581_amd as lbf
@@ -169,6 +182,9 @@ def run_ensemble(storage, steps, warmup):
     sites = ens.sites()
     out = dict(storage=storage, replicas=len(reps), sites=sites, ms_per_step=ms,
                mlups=sites / ms / 1e3, schedule=ens.schedule())
+    pooled, per = ensemble_mode_variances(ens, reps)
+    out["mode_variance_max_dev"] = max(abs(x - 1.0) for x in pooled)
+    out["mode_variance_max_dev_per_replica"] = max(abs(x - 1.0) for rr in per for x in rr)
     ens.close()
     del ens
     torch.cuda.empty_cache()

@@ -149,3 +149,29 @@ def test_contexts_on_separate_streams():
         assert lat.t == 41
         assert torch.equal(lat.state, want)
         lat.close()
+
+
+def test_ensemble_mode_variances():
+    """Every replica of the 96-replica workload (own size, kT and gamma_s)
+    keeps the stationary law var(m_k - m_k^eq) = mu_r rho w_k: per replica
+    within 1% plus its sampling error, and pooled over all replicas
+    (site-weighted, ~30 M sites) within 1%."""
+    import bench
+    reps = workloads.ensemble_replicas()
+    ens = lbf.Ensemble(reps, init="thermal")
+    n_snap = 10
+    acc = None
+    for _ in range(n_snap):
+        ens.step(25)
+        pooled, per = bench.ensemble_mode_variances(ens, reps)
+        per = np.array(per)
+        acc = per if acc is None else acc + per
+    ens.close()
+    per = acc / n_snap
+    sizes = np.array([r["nx"] * r["ny"] * r["nz"] for r in reps], dtype=float)
+    pooled = (per * sizes[:, None]).sum(axis=0) / sizes.sum()
+    say(f"ensemble: pooled max |ratio - 1| {np.abs(pooled - 1).max():.2e}, "
+        f"per-replica max {np.abs(per - 1).max():.2e}")
+    assert np.abs(pooled - 1).max() < 0.01
+    tol = 0.01 + 6 * np.sqrt(2.0 / sizes) / np.sqrt(n_snap / 2)
+    assert (np.abs(per - 1) < tol[:, None]).all()
