@@ -102,7 +102,8 @@ enum lb_thermal_modes {
 
 typedef struct {
   int32_t nx, ny, nz;     /* periodic box, each >= 1 (1 makes that axis trivial); */
-                          /* nz = 1 for D2Q9                                      */
+                          /* nz = 1 for D2Q9; at most 2^32 - 1024 sites           */
+                          /* (LB_EUNSUPPORTED above)                              */
   int32_t storage;        /* enum lb_storage                                      */
   double rho0;            /* > 0: reference density and deviation base            */
   double kT;              /* >= 0: mu = 3 kT; kT = 0 gives the deterministic update */

@@ -48,7 +48,9 @@ int validate(const lb_params* p) {
   if (p->lattice != LB_D3Q19 && p->lattice != LB_D2Q9) return fail(LB_EINVAL, "unknown lattice");
   if (p->lattice == LB_D2Q9 && p->nz != 1) return fail(LB_EINVAL, "a D2Q9 lattice needs nz = 1");
   const uint64_t n = (uint64_t)p->nx * (uint64_t)p->ny * (uint64_t)p->nz;
-  if (n >= (1ull << 32)) return fail(LB_EUNSUPPORTED, "lattices of 2^32 sites or more are not supported");
+  // site indices are 32-bit, and a grid rounded up to whole workgroups must not wrap them
+  if (n > (1ull << 32) - 1024)
+    return fail(LB_EUNSUPPORTED, "lattices of more than 2^32 - 1024 sites are not supported");
   return LB_OK;
 }
 
@@ -165,12 +167,23 @@ void* rows_ptr(int lattice, int storage, int parity, int block) {
   return lattice == LB_D2Q9 ? rows_ptr_m<D2Q9>(storage, parity, block) : rows_ptr_m<D3Q19>(storage, parity, block);
 }
 
-enum KernelKind { KK_INIT, KK_GATHER, KK_CHECK };
+// Initial states (rest, thermal, fields), gathers (populations, moments,
+// modes) and the health check; init and gather kinds are template
+// parameters of their kernels.
+enum KernelKind {
+  KK_INIT_REST, KK_INIT_THERMAL, KK_INIT_FIELDS,
+  KK_GATHER_POPULATIONS, KK_GATHER_MOMENTS, KK_GATHER_MODES,
+  KK_CHECK
+};
 template <class M, int S, int P, bool W>
 void* aux_ptr3(KernelKind kk) {
   switch (kk) {
-    case KK_INIT: return (void*)&k_init<M, S, P, W>;
-    case KK_GATHER: return (void*)&k_gather<M, S, P, W>;
+    case KK_INIT_REST: return (void*)&k_init<M, S, P, W, 0>;
+    case KK_INIT_THERMAL: return (void*)&k_init<M, S, P, W, 1>;
+    case KK_INIT_FIELDS: return (void*)&k_init<M, S, P, W, 2>;
+    case KK_GATHER_POPULATIONS: return (void*)&k_gather<M, S, P, W, 0>;
+    case KK_GATHER_MOMENTS: return (void*)&k_gather<M, S, P, W, 1>;
+    case KK_GATHER_MODES: return (void*)&k_gather<M, S, P, W, 2>;
     case KK_CHECK: return (void*)&k_check<M, S, P, W>;
   }
   return nullptr;
@@ -426,12 +439,12 @@ void free_ctx(lb_ctx* c) {
 int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity) {
   const lb_params& p = c->reps[idx];
   const uint32_t n = (uint32_t)sites_of(p);
-  void* fn = aux_ptr(KK_INIT, c->lattice, c->storage, parity, c->wide);
+  const KernelKind kk = kind == LB_INIT_REST ? KK_INIT_REST : kind == LB_INIT_THERMAL ? KK_INIT_THERMAL : KK_INIT_FIELDS;
+  void* fn = aux_ptr(kk, c->lattice, c->storage, parity, c->wide);
   const LatDesc* L = c->d_lats + idx;
-  int k = kind;
   const float* f = d_fields;
-  void* args[] = {&L, &k, &f};
-  HIP_TRY(hipLaunchKernel(fn, dim3((n + 255) / 256), dim3(256), args, 0, c->stream));
+  void* args[] = {&L, &f};
+  HIP_TRY(hipLaunchKernel(fn, dim3((uint32_t)(((uint64_t)n + 255) / 256)), dim3(256), args, 0, c->stream));
   return LB_OK;
 }
 
@@ -462,12 +475,12 @@ int gather(lb_ctx* c, int what, float* d_out) {
   if (r->reps.size() > 1 && !c->parent) return fail(LB_EINVAL, "gathers on a batch need a view (lb_batch_view)");
   HIP_TRY(hipSetDevice(r->device));
   const uint32_t n = (uint32_t)sites_of(r->reps[v.idx]);
-  void* fn = aux_ptr(KK_GATHER, r->lattice, r->storage, (int)(r->t & 1), r->wide);
+  const KernelKind kk = what == 0 ? KK_GATHER_POPULATIONS : what == 1 ? KK_GATHER_MOMENTS : KK_GATHER_MODES;
+  void* fn = aux_ptr(kk, r->lattice, r->storage, (int)(r->t & 1), r->wide);
   const LatDesc* L = r->d_lats + v.idx;
-  int w = what;
   float* o = d_out;
-  void* args[] = {&L, &w, &o};
-  HIP_TRY(hipLaunchKernel(fn, dim3((n + 255) / 256), dim3(256), args, 0, r->stream));
+  void* args[] = {&L, &o};
+  HIP_TRY(hipLaunchKernel(fn, dim3((uint32_t)(((uint64_t)n + 255) / 256)), dim3(256), args, 0, r->stream));
   return LB_OK;
 }
 

@@ -493,21 +493,25 @@ __device__ __forceinline__ void store_site(const LatDesc& L, uint32_t site, cons
   }
 }
 
-// kind 0: rest; kind 1: thermal (stream 1, normal k -> mode k);
-// kind 2: n_i^eq(rho, u) from fields (1 + d, nz, ny, nx) = rho, ux, uy[, uz].
-template <class M, int S, int P, bool WIDE>
+// KIND 0: rest; KIND 1: thermal (stream 1, normal k -> mode k);
+// KIND 2: n_i^eq(rho, u) from fields (1 + d, nz, ny, nx) = rho, ux, uy[, uz].
+// The kind is a template parameter, so every init kernel is straight-line
+// code: with 64-bit offsets, a run-time branch over the kinds merging into
+// one shared store sequence compiled to stores whose offset register the
+// fields branch never wrote.
+template <class M, int S, int P, bool WIDE, int KIND>
 __global__ void __launch_bounds__(256)
-k_init(const LatDesc* __restrict__ Lp, int kind, const float* __restrict__ fields) {
+k_init(const LatDesc* __restrict__ Lp, const float* __restrict__ fields) {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   constexpr int Q = M::Q;
   const LatDesc& L = *Lp;
   const uint32_t site = blockIdx.x * 256u + threadIdx.x;
   if (site >= L.nsites) return;
   float d[Q];
-  if (kind == 0) {
+  if constexpr (KIND == 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) d[i] = 0.0f;
-  } else if (kind == 1) {
+  } else if constexpr (KIND == 1) {
     constexpr int NP = (Q + 1) / 2;         // Box-Muller pairs
     constexpr int NT = (2 * NP + 3) / 4;    // word triples
     constexpr int NC = (3 * NT + 3) / 4;    // Philox calls
@@ -542,10 +546,11 @@ k_init(const LatDesc* __restrict__ Lp, int kind, const float* __restrict__ field
 }
 
 // ---------------------------------------------------------------- gathers
-// what: 0 populations n_i (q planes), 1 moments rho, j (1 + d planes), 2 modes m_k (q planes).
-template <class M, int S, int P, bool WIDE>
+// WHAT: 0 populations n_i (q planes), 1 moments rho, j (1 + d planes), 2 modes
+// m_k (q planes); a template parameter for the same reason as init's kind.
+template <class M, int S, int P, bool WIDE, int WHAT>
 __global__ void __launch_bounds__(256)
-k_gather(const LatDesc* __restrict__ Lp, int what, float* __restrict__ out) {
+k_gather(const LatDesc* __restrict__ Lp, float* __restrict__ out) {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   constexpr int Q = M::Q;
   const LatDesc& L = *Lp;
@@ -555,7 +560,7 @@ k_gather(const LatDesc* __restrict__ Lp, int what, float* __restrict__ out) {
   float d[Q];
   Off o[Q];
   load_site<M, S, P>(L, site, d, o);
-  if (what == 0) {
+  if constexpr (WHAT == 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const float ar = (M::A36[i] / 36.0f) * L.rho0;
@@ -565,7 +570,7 @@ k_gather(const LatDesc* __restrict__ Lp, int what, float* __restrict__ out) {
     float mu[Q];
     M::forward(d, mu);
     const float s = L.rho0 * (1.0f / 36.0f);
-    if (what == 1) {
+    if constexpr (WHAT == 1) {
       out[site] = __builtin_fmaf(s, mu[0], L.rho0);
 #pragma unroll
       for (int a = 1; a <= M::D; ++a) out[a * N + site] = s * mu[a];
@@ -588,7 +593,9 @@ k_check(const LatDesc* __restrict__ Lp, double* __restrict__ partial) {
   constexpr int Q = M::Q;
   const LatDesc& L = *Lp;
   double acc[5] = {0, 0, 0, 0, 0};  // bad sites, rho - rho0, jx, jy, jz (0 in 2D)
-  for (uint32_t site = blockIdx.x * 256u + threadIdx.x; site < L.nsites; site += gridDim.x * 256u) {
+  // 64-bit loop counter: the stride would wrap a 32-bit site index near 2^32
+  for (uint64_t i = blockIdx.x * 256u + threadIdx.x; i < L.nsites; i += (uint64_t)gridDim.x * 256u) {
+    const uint32_t site = (uint32_t)i;
     float d[Q];
     Off o[Q];
     load_site<M, S, P>(L, site, d, o);

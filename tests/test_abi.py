@@ -78,6 +78,14 @@ def test_too_many_sites_unsupported():
     ctx = ctypes.c_void_p()
     assert L.lb_init(ctypes.byref(p), ctypes.c_void_p(256), None, 0, None, 0,
                      ctypes.byref(ctx)) == lb.LB_EUNSUPPORTED
+    # just below 2^32, but a grid of whole workgroups would wrap the 32-bit site index
+    p = lb.make_params(512, 8388607, 1, storage="f16", lattice="d2q9")
+    assert L.lb_state_bytes(ctypes.byref(p)) == 0
+    assert L.lb_init(ctypes.byref(p), ctypes.c_void_p(256), None, 0, None, 0,
+                     ctypes.byref(ctx)) == lb.LB_EUNSUPPORTED
+    # the largest size used by the tests is accepted
+    p = lb.make_params(65536, 65535, 1, storage="f16", lattice="d2q9")
+    assert L.lb_state_bytes(ctypes.byref(p)) == 9 * 65536 * 65535 * 2
 
 
 def test_other_argument_errors():

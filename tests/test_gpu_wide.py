@@ -36,3 +36,51 @@ def test_1024_fp32_wide_planes_sampled_parity():
     check_one_step(lat, cfg, pts, 1e-5)      # odd step
     assert lat.check()[0] == 0
     lat.close()
+
+
+def test_largest_site_count_d2q9_f16():
+    """The largest lattice the 32-bit site index allows: D2Q9 65536 x 65535
+    (4,294,901,760 sites, just below 2^32; fp16 planes of 8.6 GB, so the
+    64-bit-offset kernels run).  A kT = 0 shear wave u_x(y) is independent
+    of x, so sampled sites up to the last site index must follow the FP64
+    1 x 65535 reduction (up to fp16 storage rounding) at both parities."""
+    free, total = torch.cuda.mem_get_info()
+    if free < 200 * 2 ** 30:
+        pytest.skip("needs about 180 GB of free device memory")
+    import oracle
+    import workloads
+    nx, ny, U, periods = 65536, 65535, 1e-2, 5
+    cfg = dict(nx=nx, ny=ny, nz=1, rho0=1.0, kT=0.0, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=0.0,
+               gamma_even=0.0, seed=0, lattice="d2q9")
+    say("D2Q9 65536 x 65535 fp16 (site index up to 2^32 - 65537)")
+    f = torch.zeros((3, 1, ny, nx), dtype=torch.float32, device="cuda")
+    f[0] = 1.0
+    y = torch.arange(ny, device="cuda", dtype=torch.float64)
+    f[1, 0] = (U * torch.sin(2 * np.pi * periods * y / ny)).float()[:, None]
+    lat = lbf.Lattice(**cfg, storage="f16", init="fields", fields=f)
+    torch.cuda.synchronize()
+    del f
+    lat._fields = None
+    torch.cuda.empty_cache()
+    p = oracle.params(1, ny, 1, rho0=1.0, kT=0.0, gamma_bulk=0.5, gamma_shear=0.8, lattice=oracle.D2Q9)
+    n = oracle.init(p, oracle.INIT_FIELDS,
+                    workloads.shear_wave_fields_2d(1, ny, U, periods).astype(np.float64))
+    rng = np.random.default_rng(3)
+    xs = np.concatenate([rng.integers(0, nx, 400), [0, nx - 1, nx - 1, 0, nx - 1]])
+    ys = np.concatenate([rng.integers(0, ny, 400), [0, ny - 1, 0, ny - 1, ny - 2]])
+    t = 0
+    for target in (1, 2, 3):
+        lat.step(target - t)
+        n = oracle.run(p, n, t, target - t)
+        t = target
+        mom = lat.moments()
+        got = mom[1, 0, torch.as_tensor(ys, device="cuda"), torch.as_tensor(xs, device="cuda")].double().cpu().numpy()
+        del mom
+        torch.cuda.empty_cache()
+        want = oracle.moments(p, n)[1, 0, ys, 0]
+        err = float(np.abs(got - want).max())
+        say(f"  t={t}: max |jx - jx_oracle| = {err:.3e} (U = {U})")
+        assert err < 1e-2 * U, (t, err)
+    nb, sums = lat.check()
+    assert nb == 0
+    lat.close()
