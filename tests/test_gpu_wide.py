@@ -35,6 +35,20 @@ def test_1024_fp32_wide_planes_sampled_parity():
     lat.step(18)                             # one direct step, one 16-step graph replay, one more: t = 19
     check_one_step(lat, cfg, pts, 1e-5)      # odd step
     assert lat.check()[0] == 0
+    # the modes gather of the wide kernels agrees with the projected populations
+    import oracle
+    c, a, e, w = oracle.tables()
+    idx = torch.as_tensor(pts, device="cuda")
+    pops = lat.populations()
+    n = pops[:, idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    del pops
+    torch.cuda.empty_cache()
+    modes = lat.modes()
+    m = modes[:, idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    del modes
+    torch.cuda.empty_cache()
+    want = e @ (n - a[:, None] * cfg["rho0"])
+    assert np.abs(m - want).max() < 1e-5, np.abs(m - want).max()  # fp32 rounding of the absolute n_i
     lat.close()
 
 
