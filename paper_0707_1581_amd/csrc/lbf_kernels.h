@@ -239,13 +239,68 @@ __device__ __forceinline__ void st(const LatDesc& L, int plane, Off o, T v) {
 }
 
 // Policy chosen per plane; `nt` is a constant once the plane loops unroll.
-template <class T, class Off>
-__device__ __forceinline__ T ld_sel(const LatDesc& L, int plane, Off o, bool nt) {
+// Buffer accesses only: the policy is an immediate operand of the buffer
+// intrinsic, so the two branches stay distinct.  Two global accesses of the
+// same address that differ only in the non-temporal hint are merged by the
+// optimiser into one access without it, so the 64-bit-offset path loops with
+// the plane index as a compile-time constant instead (static_for) and passes
+// the policy as a template argument.
+template <class T>
+__device__ __forceinline__ T ld_sel(const LatDesc& L, int plane, uint32_t o, bool nt) {
   return nt ? ld<T, CPOL_NT>(L, plane, o) : ld<T, 0>(L, plane, o);
 }
-template <class T, class Off>
-__device__ __forceinline__ void st_sel(const LatDesc& L, int plane, Off o, T v, bool nt) {
+template <class T>
+__device__ __forceinline__ void st_sel(const LatDesc& L, int plane, uint32_t o, T v, bool nt) {
   if (nt) st<T, CPOL_NT>(L, plane, o, v); else st<T, 0>(L, plane, o, v);
+}
+
+constexpr int pol(bool nt) { return nt ? CPOL_NT : 0; }
+template <int N> struct Idx { static constexpr int value = N; };
+template <int B, int E, int STEP = 1, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(Idx<B>{});
+    static_for<B + STEP, E, STEP>(f);
+  }
+}
+
+// 16-bit storage, planes below 4 GiB: the two members of an opposite pair are
+// converted together (one packed conversion) and stored through global
+// stores with a uniform plane address and a 32-bit lane byte offset; the
+// second value leaves from the high half of the register (a d16_hi store), so
+// a pair costs one conversion instruction and no shift.  Bits are the same as
+// Codec<S>::enc (round to nearest even).
+template <int S> struct Half2;
+template <> struct Half2<ST_F16> {
+  using E = _Float16;
+  using V = _Float16 __attribute__((ext_vector_type(2)));
+};
+template <> struct Half2<ST_BF16> {
+  using E = __bf16;
+  using V = __bf16 __attribute__((ext_vector_type(2)));
+};
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ LBF_GLOBAL char* plane_ptr(const LatDesc& L, int plane, uint32_t esize) {
+  return (LBF_GLOBAL char*)(uintptr_t)(L.base + (uint64_t)plane * L.plane * esize);
+}
+
+// pa + ba <- a, pb + bb <- b, both with cache policy POL (the two members of
+// an opposite pair have the same one).
+template <int S, int POL>
+__device__ __forceinline__ void st_pair16(LBF_GLOBAL char* pa, uint32_t ba, float a, LBF_GLOBAL char* pb,
+                                          uint32_t bb, float b) {
+  using H = Half2<S>;
+  const typename H::V v = __builtin_convertvector((f32x2){a, b}, typename H::V);
+  LBF_GLOBAL typename H::E* qa = (LBF_GLOBAL typename H::E*)(pa + ba);
+  LBF_GLOBAL typename H::E* qb = (LBF_GLOBAL typename H::E*)(pb + bb);
+  if constexpr (POL == CPOL_NT) {
+    __builtin_nontemporal_store(v.x, qa);
+    __builtin_nontemporal_store(v.y, qb);
+  } else {
+    *qa = v.x;
+    *qb = v.y;
+  }
 }
 
 // Load the q populations (as d_i) of site r of the state at parity P.
@@ -253,16 +308,22 @@ template <class M, int S, int P, class Off>
 __device__ __forceinline__ void load_site(const LatDesc& L, uint32_t site, float d[M::Q], Off o[M::Q]) {
   using C = Codec<S>;
   using CP = CachePolicy<M, S, P>;
+  using T = typename C::T;
   if (P == 0) {
 #pragma unroll
     for (int j = 0; j < M::Q; ++j) o[j] = (Off)site;
-#pragma unroll
-    for (int i = 0; i < M::Q; ++i) d[i] = C::dec(ld_sel<typename C::T>(L, i, o[i], CP::nt_load(i)));
   } else {
     neighbour_offsets<M>(L, site, o);
-    // plane j at r + c_j holds population opp(j) of site r
+  }
+  // at the odd step plane j at r + c_j holds population opp(j) of site r
+  if constexpr (sizeof(Off) == 4) {
 #pragma unroll
-    for (int j = 0; j < M::Q; ++j) d[M::OPP[j]] = C::dec(ld_sel<typename C::T>(L, j, o[j], CP::nt_load(j)));
+    for (int j = 0; j < M::Q; ++j) d[P == 0 ? j : M::OPP[j]] = C::dec(ld_sel<T>(L, j, o[j], CP::nt_load(j)));
+  } else {
+    static_for<0, M::Q>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      d[P == 0 ? j : M::OPP[j]] = C::dec(ld<T, pol(CP::nt_load(j))>(L, j, o[j]));
+    });
   }
 }
 
@@ -374,13 +435,34 @@ k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint3
   Off o[Q];
   load_site<M, S, P>(L, site, d, o);
   collide<M>(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
-  if (P == 0) {
+  using CP = CachePolicy<M, S, P>;
+  using T = typename C::T;
+  if constexpr (S != ST_F32 && !WIDE && P == 1) {
+    // rest population alone, then the opposite pairs (i, i + 1), i odd, packed;
+    // population j goes to plane j at r + c_j.  (At the even step, where every
+    // store of the site has the same offset, plain buffer stores measure a
+    // little faster.)
+    st<T, pol(CP::nt_store(0))>(L, 0, o[0], C::enc(d[0]));
+    static_for<1, Q, 2>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      static_assert(CP::nt_store(i) == CP::nt_store(i + 1), "pair members share a policy");
+      st_pair16<S, pol(CP::nt_store(i))>(plane_ptr(L, i, 2), (uint32_t)o[i] * 2u, d[i], plane_ptr(L, i + 1, 2),
+                                         (uint32_t)o[i + 1] * 2u, d[i + 1]);
+    });
+  } else if constexpr (!WIDE) {
+    // population i goes to plane opp(i) at r (even) or to plane i at r + c_i (odd)
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      st_sel(L, M::OPP[i], o[i], C::enc(d[i]), CachePolicy<M, S, 0>::nt_store(M::OPP[i]));
+    for (int i = 0; i < Q; ++i) {
+      constexpr bool even = P == 0;
+      const int plane = even ? M::OPP[i] : i;
+      st_sel(L, plane, o[i], C::enc(d[i]), CP::nt_store(plane));
+    }
   } else {
-#pragma unroll
-    for (int j = 0; j < Q; ++j) st_sel(L, j, o[j], C::enc(d[j]), CachePolicy<M, S, 1>::nt_store(j));
+    static_for<0, Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int plane = P == 0 ? M::OPP[i] : i;
+      st<T, pol(CP::nt_store(plane))>(L, plane, o[i], C::enc(d[i]));
+    });
   }
 }
 
@@ -450,19 +532,40 @@ k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
     }
   }
   collide<M>(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
-  if (P == 0) {
+  // uniform row offset (elements) and lane byte offset of plane j at r + c_j
+  auto row_of = [&](int j) {
+    uint32_t ro = r0;
+    if (M::CY[j] > 0) ro += yp;
+    if (M::CY[j] < 0) ro += ym;
+    if (M::CZ[j] > 0) ro += zp;
+    if (M::CZ[j] < 0) ro += zm;
+    return ro;
+  };
+  auto lane_of = [&](int j) { return M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx); };
+  if constexpr (S != ST_F32) {
+    // rest population alone, then the opposite pairs (i, i + 1), i odd, packed
+    if (P == 0) {
+      Raw<T>::template st<CPOL_NT>(plane_rsrc(L, 0, ES), bx, C::enc(d[0]), r0 * ES);
+#pragma unroll
+      for (int i = 1; i < Q; i += 2)
+        st_pair16<S, CPOL_NT>(plane_ptr(L, i + 1, ES) + r0 * ES, bx, d[i], plane_ptr(L, i, ES) + r0 * ES, bx, d[i + 1]);
+    } else {
+      Raw<T>::template st<CPOL_NT>(plane_rsrc(L, 0, ES), bx, C::enc(d[0]), r0 * ES);
+      static_for<1, Q, 2>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        static_assert(CP::nt_store(i) == CP::nt_store(i + 1), "pair members share a policy");
+        st_pair16<S, pol(CP::nt_store(i))>(plane_ptr(L, i, ES) + row_of(i) * ES, lane_of(i), d[i],
+                                           plane_ptr(L, i + 1, ES) + row_of(i + 1) * ES, lane_of(i + 1), d[i + 1]);
+      });
+    }
+  } else if (P == 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i)
       Raw<T>::template st<CPOL_NT>(plane_rsrc(L, M::OPP[i], ES), bx, C::enc(d[i]), r0 * ES);
   } else {
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      uint32_t ro = r0;
-      if (M::CY[j] > 0) ro += yp;
-      if (M::CY[j] < 0) ro += ym;
-      if (M::CZ[j] > 0) ro += zp;
-      if (M::CZ[j] < 0) ro += zm;
-      const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
+      const uint32_t ro = row_of(j), vx = lane_of(j);
       if (CP::nt_store(j)) Raw<T>::template st<CPOL_NT>(plane_rsrc(L, j, ES), vx, C::enc(d[j]), ro * ES);
       else Raw<T>::template st<0>(plane_rsrc(L, j, ES), vx, C::enc(d[j]), ro * ES);
     }
