@@ -221,12 +221,16 @@ int lb_get_schedule(const lb_ctx* ctx, lb_schedule* out);
 int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
 
 /* Time every candidate schedule on a scratch copy of the state (the state
- * and step count of ctx are unchanged): for each block size and tile order,
- * every (xcd_remap in {0, 1, 2, 4, 8}, tiling) pair is timed on even and on odd steps
- * separately (`steps` >= 2 launches of each parity), and the fastest pair is
- * kept per parity.  Applies the best schedule and writes a JSON report (one
- * object per candidate with its mean even and odd step times) into report
- * (NUL-terminated, truncated to report_len). */
+ * and step count of ctx are unchanged): every block size and tile order
+ * with every (xcd_remap in {0, 1, 2, 4, 8}, tiling) pair, timed on even and
+ * on odd steps separately (`steps` >= 2 launches of each parity).  The six
+ * fastest candidates of each parity are then timed again in three
+ * interleaved rounds, and the choice rests on those times: the block size
+ * and order whose fastest even and odd (remap, tiling) choices sum lowest.
+ * Applies the best schedule and writes a JSON report (one object per
+ * candidate with its mean even and odd step times, plus refined_even_ms /
+ * refined_odd_ms for the re-timed ones) into report (NUL-terminated,
+ * truncated to report_len).  Allocates a scratch copy of the state. */
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
 
 #ifdef __cplusplus

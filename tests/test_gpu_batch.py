@@ -81,6 +81,14 @@ def test_autotune_leaves_state_and_counter_unchanged():
     before = ens.pool.clone()
     rep = json.loads(ens.autotune(steps=4))
     assert len(rep) == 4 * 3 * 5 * 2 and all(c["even_ms"] > 0 and c["odd_ms"] > 0 for c in rep)
+    # the six fastest of each parity are re-timed, and the choice is made among them
+    refined = [c for c in rep if "refined_even_ms" in c]
+    assert 6 <= len(refined) <= 12 and all(c["refined_even_ms"] > 0 and c["refined_odd_ms"] > 0 for c in refined)
+    sched = ens.schedule()
+    for q, key in enumerate(("refined_even_ms", "refined_odd_ms")):
+        mine = [c for c in refined if c["block"] == sched["block"] and c["order"] == sched["order"]]
+        best = min(mine, key=lambda c: c[key])
+        assert (best["xcd_remap"], best["tiling"]) == (sched["xcd_remap"][q], sched["tiling"][q])
     assert ens.t == 3
     assert torch.equal(ens.pool, before)
     ens.step(10)
