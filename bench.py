@@ -21,6 +21,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -33,15 +34,22 @@ W36_D2Q9 = [36, 12, 12, 144, 16, 4, 24, 24, 576]  # 36 w_k, Table I
 KERNEL_SOURCES = ["paper_0707_1581_amd/csrc/lbf_kernels.h", "paper_0707_1581_amd/csrc/lbf_math.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_aa_step_512.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_step.json")
-# VALU issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (fp32 vector 157.3 TFLOP/s = 2 x 2 x this)
-VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
+# VALU issue budget: 256 CUs x 4 SIMDs at 2.4 GHz; a wave64 fp32 add/mul/fma issues in 2 cycles,
+# conversions and integer multiplies in 4, transcendentals in 8 (measured on gfx950)
+VALU_SIMD_CYCLES = 256 * 4 * 2.4e9
 
 
 def kernel_hash():
+    """Hash of the kernel sources with comments and blank space removed, so
+    that a stored counter value stays tied to the code it was taken on and
+    not to the wording of its comments."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
@@ -59,21 +67,25 @@ def stored_traffic(storage):
 
 
 def stored_valu(key, mlups):
-    """VALU figure of a run: instructions per site-update from the SQ_INSTS_VALU
-    counter (stored with the kernel-source hash; mean of the default
-    schedule's even and odd kernels) times the measured site-update rate,
-    against the VALU issue peak."""
+    """VALU figures of a run: instructions per site-update from the
+    SQ_INSTS_VALU counter and issue cycles per wave (the instruction mix of
+    the gfx950 assembly weighted by measured issue costs), both stored with
+    the kernel-source hash as the mean of the default schedule's even and
+    odd kernels, and the fraction of the VALU issue cycles the measured
+    site-update rate keeps busy."""
     try:
         with open(VALU_FILE) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_hash") != kernel_hash() or key not in rec.get("valu_instr_per_site", {}):
+    if (rec.get("kernel_hash") != kernel_hash() or key not in rec.get("valu_instr_per_site", {})
+            or key not in rec.get("issue_cycles_per_wave", {})):
         return None
     ips = rec["valu_instr_per_site"][key]
-    achieved = ips * mlups * 1e6
-    return {"bound": "alu", "instr_per_site": ips, "achieved": achieved, "peak": VALU_PEAK_LANE_INSTR,
-            "unit": "lane-instructions/s", "frac": achieved / VALU_PEAK_LANE_INSTR}
+    cyc = rec["issue_cycles_per_wave"][key]
+    busy = cyc * mlups * 1e6 / 64 / VALU_SIMD_CYCLES
+    return {"instr_per_site": ips, "issue_cycles_per_wave": cyc, "busy_frac": busy,
+            "source": "profiles/k_step_valu.md"}
 
 
 def time_steps(step, steps, warmup, sync_stream):

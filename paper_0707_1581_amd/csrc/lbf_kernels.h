@@ -171,8 +171,8 @@ __device__ __forceinline__ void neighbour_offsets(const LatDesc& L, uint32_t sit
 // so non-temporal (streaming) loads and stores bring it close to the bandwidth
 // of pure data movement; the odd step's x-shifted accesses share cache lines
 // between neighbouring waves, which non-temporal loads would evict early, so
-// it keeps them cached (fp32) -- except for the VALU-bound 16-bit forms, where
-// non-temporal loads with cached stores measured fastest.
+// it keeps those planes cached and streams the others.  The same policy
+// measured fastest for all three storage types.
 #define LBF_GLOBAL __attribute__((address_space(1)))
 constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
 constexpr int RAW_BUFFER_WORD3 = 0x00020000;
