@@ -164,6 +164,12 @@ def run_lattice(dims, storage, steps, warmup, cfg, check=True, tune=True, lattic
         nb, sums = lat.check()
         out["bad_sites"] = nb
         out["mode_variance_max_dev"] = mode_variance_dev(lat, cfg["rho0"], cfg["kT"], lattice)
+    # the data-movement floor of the same box and schedule: propagation-only
+    # steps (the same tiles, accesses and cache policy, no collision), timed
+    # after the checks
+    pm = time_steps(lat.propagate, min(steps, 40), 4, lat.stream)
+    out["propagate_only"] = {"ms_per_step": pm, "achieved_gbs": alg / pm / 1e6,
+                             "step_speed_frac": pm / ms}
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -418,6 +424,12 @@ def main():
                 "kernel": "fp32 step kernel (lbf::k_step / lbf::k_step_rows as scheduled; even and odd "
                           "AA launches; mean launch duration)",
                 "alg_bytes_per_launch": main_run["alg_bytes_per_launch"]}
+    # the data-movement floor of the timed step: the same launches without the
+    # collision (lb_propagate, same schedule, accesses and cache policy)
+    prop = main_run["propagate_only"]
+    ceilings = {"propagate_only_ms_per_step": prop["ms_per_step"], "propagate_only_gbs": prop["achieved_gbs"],
+                "propagate_only_frac_of_peak": prop["achieved_gbs"] / HBM_PEAK_GBS,
+                "step_speed_frac_of_propagate_only": prop["ms_per_step"] / main_run["ms_per_step"]}
     line = {
         "metric": "MLUPS and % HBM roofline, FP32 vs 16-bit storage at 1% mode-variance error",
         "value": main_run["mlups"],
@@ -438,6 +450,7 @@ def main():
                    "mode_variance_max_dev": main_run["mode_variance_max_dev"],
                    "bad_sites": main_run["bad_sites"], "schedule": main_run["schedule"]},
         "roofline": roofline,
+        "ceilings": ceilings,
         "variants": variants,
     }
     if not args.no_cpu:

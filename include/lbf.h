@@ -133,6 +133,18 @@ int lb_init(const lb_params* p, void* d_state, void* hip_stream, int32_t init_ki
  * then push).  Full chunks of steps are replayed from a HIP graph. */
 int lb_step(lb_ctx* ctx, int64_t nsteps);
 
+/* Enqueue nsteps >= 0 propagation-only steps: the streaming half of
+ * Eq. LBE with the identity collision (what every rate gamma_k = 1 and
+ * kT = 0 would give up to rounding), n_i(r + c_i, t + 1) = n_i(r, t) for
+ * every population, periodic.  The stored values are moved unchanged, so
+ * the result is an exact permutation of the state.  The step count advances
+ * as with lb_step, keeping the parity-resolved layout consistent (later
+ * collisions draw the noise of the advanced counter).  On a batch every
+ * replica moves.  Each step is one launch over the tiles of the current
+ * schedule, with the memory accesses and cache policy of the step kernel
+ * it replaces, so its duration is the data-movement floor of that step. */
+int lb_propagate(lb_ctx* ctx, int64_t nsteps);
+
 /* Parity-resolved gathers into caller-owned fp32 device buffers, each laid
  * out (count, nz, ny, nx):
  *   lb_populations: q planes, n_i;

@@ -114,57 +114,67 @@ LatDesc make_desc(const lb_params& p, uint64_t base) {
 bool is_wide(const lb_params& p) { return sites_of(p) * elem_size(p.storage) >= (1ull << 32); }
 
 // ---------------------------------------------------------------- kernel tables
-template <class M, int S, int P, bool W>
+// Step kernels (PROP = false) and their propagation-only twins (PROP = true),
+// flat tiling.
+template <class M, int S, int P, bool W, bool PROP>
 void* step_ptr_b(int block) {
   switch (block) {
-    case 64: return (void*)&k_step<M, S, P, W, 64>;
-    case 128: return (void*)&k_step<M, S, P, W, 128>;
-    case 256: return (void*)&k_step<M, S, P, W, 256>;
-    case 512: return (void*)&k_step<M, S, P, W, 512>;
+    case 64: return PROP ? (void*)&k_propagate<M, S, P, W, 64> : (void*)&k_step<M, S, P, W, 64>;
+    case 128: return PROP ? (void*)&k_propagate<M, S, P, W, 128> : (void*)&k_step<M, S, P, W, 128>;
+    case 256: return PROP ? (void*)&k_propagate<M, S, P, W, 256> : (void*)&k_step<M, S, P, W, 256>;
+    case 512: return PROP ? (void*)&k_propagate<M, S, P, W, 512> : (void*)&k_step<M, S, P, W, 512>;
   }
   return nullptr;
 }
-template <class M, int S>
+template <class M, int S, bool PROP>
 void* step_ptr_s(int parity, bool wide, int block) {
-  if (parity) return wide ? step_ptr_b<M, S, 1, true>(block) : step_ptr_b<M, S, 1, false>(block);
-  return wide ? step_ptr_b<M, S, 0, true>(block) : step_ptr_b<M, S, 0, false>(block);
+  if (parity) return wide ? step_ptr_b<M, S, 1, true, PROP>(block) : step_ptr_b<M, S, 1, false, PROP>(block);
+  return wide ? step_ptr_b<M, S, 0, true, PROP>(block) : step_ptr_b<M, S, 0, false, PROP>(block);
 }
-template <class M>
+template <class M, bool PROP>
 void* step_ptr_m(int storage, int parity, bool wide, int block) {
   switch (storage) {
-    case LB_F32: return step_ptr_s<M, ST_F32>(parity, wide, block);
-    case LB_F16: return step_ptr_s<M, ST_F16>(parity, wide, block);
-    case LB_BF16: return step_ptr_s<M, ST_BF16>(parity, wide, block);
+    case LB_F32: return step_ptr_s<M, ST_F32, PROP>(parity, wide, block);
+    case LB_F16: return step_ptr_s<M, ST_F16, PROP>(parity, wide, block);
+    case LB_BF16: return step_ptr_s<M, ST_BF16, PROP>(parity, wide, block);
   }
   return nullptr;
 }
-void* step_ptr(int lattice, int storage, int parity, bool wide, int block) {
-  return lattice == LB_D2Q9 ? step_ptr_m<D2Q9>(storage, parity, wide, block)
-                            : step_ptr_m<D3Q19>(storage, parity, wide, block);
+void* step_ptr(int lattice, int storage, int parity, bool wide, int block, bool prop) {
+  if (prop)
+    return lattice == LB_D2Q9 ? step_ptr_m<D2Q9, true>(storage, parity, wide, block)
+                              : step_ptr_m<D3Q19, true>(storage, parity, wide, block);
+  return lattice == LB_D2Q9 ? step_ptr_m<D2Q9, false>(storage, parity, wide, block)
+                            : step_ptr_m<D3Q19, false>(storage, parity, wide, block);
 }
 
-// Row-tiled step kernels (non-wide lattices only).
-template <class M, int S, int P>
+// Row-tiled step kernels and their propagation-only twins (non-wide
+// lattices only).
+template <class M, int S, int P, bool PROP>
 void* rows_ptr_b(int block) {
   switch (block) {
-    case 64: return (void*)&k_step_rows<M, S, P, 64>;
-    case 128: return (void*)&k_step_rows<M, S, P, 128>;
-    case 256: return (void*)&k_step_rows<M, S, P, 256>;
-    case 512: return (void*)&k_step_rows<M, S, P, 512>;
+    case 64: return PROP ? (void*)&k_propagate_rows<M, S, P, 64> : (void*)&k_step_rows<M, S, P, 64>;
+    case 128: return PROP ? (void*)&k_propagate_rows<M, S, P, 128> : (void*)&k_step_rows<M, S, P, 128>;
+    case 256: return PROP ? (void*)&k_propagate_rows<M, S, P, 256> : (void*)&k_step_rows<M, S, P, 256>;
+    case 512: return PROP ? (void*)&k_propagate_rows<M, S, P, 512> : (void*)&k_step_rows<M, S, P, 512>;
   }
   return nullptr;
 }
-template <class M>
+template <class M, bool PROP>
 void* rows_ptr_m(int storage, int parity, int block) {
   switch (storage) {
-    case LB_F32: return parity ? rows_ptr_b<M, ST_F32, 1>(block) : rows_ptr_b<M, ST_F32, 0>(block);
-    case LB_F16: return parity ? rows_ptr_b<M, ST_F16, 1>(block) : rows_ptr_b<M, ST_F16, 0>(block);
-    case LB_BF16: return parity ? rows_ptr_b<M, ST_BF16, 1>(block) : rows_ptr_b<M, ST_BF16, 0>(block);
+    case LB_F32: return parity ? rows_ptr_b<M, ST_F32, 1, PROP>(block) : rows_ptr_b<M, ST_F32, 0, PROP>(block);
+    case LB_F16: return parity ? rows_ptr_b<M, ST_F16, 1, PROP>(block) : rows_ptr_b<M, ST_F16, 0, PROP>(block);
+    case LB_BF16: return parity ? rows_ptr_b<M, ST_BF16, 1, PROP>(block) : rows_ptr_b<M, ST_BF16, 0, PROP>(block);
   }
   return nullptr;
 }
-void* rows_ptr(int lattice, int storage, int parity, int block) {
-  return lattice == LB_D2Q9 ? rows_ptr_m<D2Q9>(storage, parity, block) : rows_ptr_m<D3Q19>(storage, parity, block);
+void* rows_ptr(int lattice, int storage, int parity, int block, bool prop) {
+  if (prop)
+    return lattice == LB_D2Q9 ? rows_ptr_m<D2Q9, true>(storage, parity, block)
+                              : rows_ptr_m<D3Q19, true>(storage, parity, block);
+  return lattice == LB_D2Q9 ? rows_ptr_m<D2Q9, false>(storage, parity, block)
+                            : rows_ptr_m<D3Q19, false>(storage, parity, block);
 }
 
 // Initial states (rest, thermal, fields), gathers (populations, moments,
@@ -311,14 +321,17 @@ struct StepLaunch {
   int block;
   const uint32_t* blk;
 };
-StepLaunch step_launch(const lb_ctx* c, int parity) {
+StepLaunch step_launch(const lb_ctx* c, int parity, bool prop = false) {
   if (c->sched.tiling[parity])
-    return {rows_ptr(c->lattice, c->storage, parity, c->sched.block), c->grid_rows, c->sched.block, c->d_blk_rows};
-  return {step_ptr(c->lattice, c->storage, parity, c->wide, c->sched.block), c->grid, c->sched.block, c->d_blk};
+    return {rows_ptr(c->lattice, c->storage, parity, c->sched.block, prop), c->grid_rows, c->sched.block,
+            c->d_blk_rows};
+  return {step_ptr(c->lattice, c->storage, parity, c->wide, c->sched.block, prop), c->grid, c->sched.block,
+          c->d_blk};
 }
 
-int launch_step(lb_ctx* c, uint32_t t_off, int parity) {
-  const StepLaunch sl = step_launch(c, parity);
+// prop: the propagation-only kernel of the same schedule instead
+int launch_step(lb_ctx* c, uint32_t t_off, int parity, bool prop = false) {
+  const StepLaunch sl = step_launch(c, parity, prop);
   if (!sl.fn) return fail(LB_EINVAL, "no step kernel for this schedule");
   lb_ctx::StepArgs a{c->d_tile_lats, sl.blk, (uint32_t)c->lats.size(), (uint32_t)c->sched.xcd_remap[parity],
                      c->d_t, t_off};
@@ -555,6 +568,22 @@ int lb_step(lb_ctx* ctx, int64_t nsteps) {
   if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
   if (ctx->parent) return fail(LB_EINVAL, "a view cannot step; step its batch");
   return advance(ctx, nsteps);
+}
+
+int lb_propagate(lb_ctx* ctx, int64_t nsteps) {
+  if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
+  if (ctx->parent) return fail(LB_EINVAL, "a view cannot step; step its batch");
+  if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return LB_OK;
+  HIP_TRY(hipSetDevice(ctx->device));
+  for (int64_t s = 0; s < nsteps; ++s) {
+    int rc = launch_step(ctx, (uint32_t)s, (int)((ctx->t + s) & 1), true);
+    if (rc) return rc;
+  }
+  int rc = launch_advance(ctx, (uint64_t)nsteps);
+  if (rc) return rc;
+  ctx->t += nsteps;
+  return LB_OK;
 }
 
 int lb_populations(lb_ctx* ctx, float* d_out) { return gather(ctx, 0, d_out); }

@@ -572,6 +572,108 @@ k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
   }
 }
 
+// ---------------------------------------------------------------- propagation only
+// One AA step with the identity collision: every population moves from r to
+// r + c_i (periodic) and nothing else happens.  The stored values move
+// unchanged, without decoding, so the result is an exact permutation of the
+// state.  k_propagate and k_propagate_rows take the tiles, accesses and cache
+// policy of k_step and k_step_rows, so their duration is the data-movement
+// floor of the step of the same schedule.  (Their set-up code repeats that of
+// the step kernels on purpose: routing both through one shared device
+// function changed the step kernels' register allocation, with SGPR spills.)
+template <class M, int S, int P, bool WIDE, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_propagate(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
+            uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
+  using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  using T = typename Codec<S>::T;
+  using CP = CachePolicy<M, S, P>;
+  constexpr int Q = M::Q;
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, remap);
+  uint32_t l = 0;
+  if (nlat > 1) l = find_lattice(blk, nlat, b);
+  const LatDesc& L = lats[l];
+  const uint32_t b0 = (nlat > 1) ? blk[l] : 0u;
+  const uint32_t site = (b - b0) * BLOCK + threadIdx.x;
+  if (site >= L.nsites) return;
+  Off o[Q];
+  T h[Q];
+  if (P == 0) {
+#pragma unroll
+    for (int j = 0; j < Q; ++j) o[j] = (Off)site;
+  } else {
+    neighbour_offsets<M>(L, site, o);
+  }
+  // even: population i of r is plane i at r and goes to plane opp(i) at r;
+  // odd: plane j at r + c_j holds population opp(j) of r, and population j
+  // of r goes to plane j at r + c_j
+  static_for<0, Q>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    h[P == 0 ? j : M::OPP[j]] = ld<T, pol(CP::nt_load(j))>(L, j, o[j]);
+  });
+  static_for<0, Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int plane = P == 0 ? M::OPP[i] : i;
+    st<T, pol(CP::nt_store(plane))>(L, plane, o[i], h[i]);
+  });
+}
+
+template <class M, int S, int P, int BLOCK>
+__global__ void __launch_bounds__(BLOCK)
+k_propagate_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
+                 uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
+  using T = typename Codec<S>::T;
+  using CP = CachePolicy<M, S, 1>;
+  constexpr int Q = M::Q;
+  constexpr uint32_t ES = sizeof(T);
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, remap);
+  uint32_t l = 0;
+  if (nlat > 1) l = find_lattice(blk, nlat, b);
+  const LatDesc& L = lats[l];
+  const uint32_t bl = b - ((nlat > 1) ? blk[l] : 0u);
+  const uint32_t row = fastdiv(bl, L.ds_m, L.ds_s1, L.ds_s2);
+  const uint32_t x = (bl - row * L.segs) * BLOCK + threadIdx.x;
+  if (x >= L.nx) return;
+  uint32_t z = 0, y = row;
+  if constexpr (M::D == 3) {
+    z = fastdiv(row, L.dy_m, L.dy_s1, L.dy_s2);
+    y = row - z * L.ny;
+  }
+  const uint32_t r0 = row * L.nx;
+  const uint32_t bx = x * ES;
+  T h[Q];
+  if (P == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) h[i] = Raw<T>::template ld<CPOL_NT>(plane_rsrc(L, i, ES), bx, r0 * ES);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) Raw<T>::template st<CPOL_NT>(plane_rsrc(L, M::OPP[i], ES), bx, h[i], r0 * ES);
+    return;
+  }
+  const uint32_t ym = (y == 0) ? L.wy : 0u - L.nx;
+  const uint32_t yp = (y * L.nx == L.wy) ? 0u - L.wy : L.nx;
+  const uint32_t zm = (z == 0) ? L.wz : 0u - L.nxy;
+  const uint32_t zp = (z * L.nxy == L.wz) ? 0u - L.wz : L.nxy;
+  const uint32_t bxm = (x == 0 ? L.wx : x - 1u) * ES;
+  const uint32_t bxp = (x == L.wx ? 0u : x + 1u) * ES;
+  uint32_t ro[Q], vx[Q];
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    ro[j] = r0;
+    if (M::CY[j] > 0) ro[j] += yp;
+    if (M::CY[j] < 0) ro[j] += ym;
+    if (M::CZ[j] > 0) ro[j] += zp;
+    if (M::CZ[j] < 0) ro[j] += zm;
+    vx[j] = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
+    h[M::OPP[j]] = CP::nt_load(j) ? Raw<T>::template ld<CPOL_NT>(plane_rsrc(L, j, ES), vx[j], ro[j] * ES)
+                                  : Raw<T>::template ld<0>(plane_rsrc(L, j, ES), vx[j], ro[j] * ES);
+  }
+#pragma unroll
+  for (int j = 0; j < Q; ++j) {
+    if (CP::nt_store(j)) Raw<T>::template st<CPOL_NT>(plane_rsrc(L, j, ES), vx[j], h[j], ro[j] * ES);
+    else Raw<T>::template st<0>(plane_rsrc(L, j, ES), vx[j], h[j], ro[j] * ES);
+  }
+}
+
 // Advance the device step counter after a run of step kernels.
 __global__ void k_advance(uint64_t* d_t, uint64_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *d_t += n;

@@ -61,6 +61,7 @@ SIGNATURES = [
     ("lb_state_bytes", ctypes.c_size_t, [_P(LbParams)]),
     ("lb_init", ctypes.c_int, [_P(LbParams), _vp, _vp, ctypes.c_int32, _vp, ctypes.c_int64, _P(_vp)]),
     ("lb_step", ctypes.c_int, [_vp, ctypes.c_int64]),
+    ("lb_propagate", ctypes.c_int, [_vp, ctypes.c_int64]),
     ("lb_populations", ctypes.c_int, [_vp, _vp]),
     ("lb_moments", ctypes.c_int, [_vp, _vp]),
     ("lb_modes", ctypes.c_int, [_vp, _vp]),
@@ -226,6 +227,10 @@ class Lattice(_Gathers):
     def step(self, n=1):
         _check(lib().lb_step(self._ctx, int(n)), "lb_step")
 
+    def propagate(self, n=1):
+        """n propagation-only steps (no collision; an exact permutation)."""
+        _check(lib().lb_propagate(self._ctx, int(n)), "lb_propagate")
+
     def schedule(self):
         s = LbSchedule()
         _check(lib().lb_get_schedule(self._ctx, ctypes.byref(s)), "lb_get_schedule")
@@ -307,6 +312,10 @@ class Ensemble:
 
     def step(self, n=1):
         _check(lib().lb_batch_step(self._ctx, int(n)), "lb_batch_step")
+
+    def propagate(self, n=1):
+        """n propagation-only steps of every replica (no collision)."""
+        _check(lib().lb_propagate(self._ctx, int(n)), "lb_propagate")
 
     @property
     def t(self):
