@@ -242,10 +242,12 @@ def _oracle_mlups(p, sites, budget_s, threads):
     return sites * k / dt / 1e6, k, dt
 
 
-def cpu_baseline(budget_s=12.0, single_budget_s=4.0):
+def cpu_baseline(budget_s=12.0, single_budget_s=4.0, large_budget_s=4.0):
     """The FP64 oracle on the host cores: a 128^3 box from a thermal start,
     as many steps as fit in the budget (at least one), with all OpenMP
-    threads; and a 64^3 box on one thread."""
+    threads; a 256^3 box the same way (the rate of a plain CPU code barely
+    depends on the size once the state is far beyond the caches); and a
+    64^3 box on one thread."""
     import oracle
     import workloads
     keys = ("nx", "ny", "nz", "rho0", "kT", "gamma_bulk", "gamma_shear", "gamma_odd", "gamma_even", "seed")
@@ -254,12 +256,16 @@ def cpu_baseline(budget_s=12.0, single_budget_s=4.0):
     v, k, dt = _oracle_mlups(oracle.params(**{q: cfg[q] for q in keys}), 128 ** 3, budget_s, nthreads)
     c1 = dict(cfg, nx=64, ny=64, nz=64)
     v1, k1, dt1 = _oracle_mlups(oracle.params(**{q: c1[q] for q in keys}), 64 ** 3, single_budget_s, 1)
+    c2 = dict(cfg, nx=256, ny=256, nz=256)
+    v2, k2, dt2 = _oracle_mlups(oracle.params(**{q: c2[q] for q in keys}), 256 ** 3, large_budget_s, nthreads)
     oracle.set_num_threads(nthreads)
     return {"value": v, "unit": "MLUPS", "cores": nthreads, "kind": "oracle",
             "sample": f"128^3 box, thermal start, kT=1e-4, gamma_shear=0.8, {k} steps after 1 warm-up "
                       f"step, FP64 two-buffer push, {dt:.1f} s",
             "single_thread": {"value": v1, "unit": "MLUPS",
                               "sample": f"64^3 box, same parameters, {k1} steps on 1 thread, {dt1:.1f} s"},
+            "box_256": {"value": v2, "unit": "MLUPS", "cores": nthreads,
+                        "sample": f"256^3 box, same parameters, {k2} steps after 1 warm-up step, {dt2:.1f} s"},
             "host": host_info()}
 
 
