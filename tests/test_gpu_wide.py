@@ -3,7 +3,7 @@ exactly 4 GiB, 81.6 GB of state) leave the buffer-descriptor path, whose
 range is a 32-bit byte count, and run the 64-bit-offset global-memory
 kernels.  Parity on sampled sites against the oracle's single-site update,
 both AA parities, with the default schedule (flat tiling; the row tiling is
-refused for such planes)."""
+refused for such planes); propagation-only steps as exact shifts."""
 import numpy as np
 import pytest
 import torch
@@ -49,6 +49,21 @@ def test_1024_fp32_wide_planes_sampled_parity():
     torch.cuda.empty_cache()
     want = e @ (n - a[:, None] * cfg["rho0"])
     assert np.abs(m - want).max() < 1e-5, np.abs(m - want).max()  # fp32 rounding of the absolute n_i
+    # propagation only on the 64-bit-offset kernels, both parities: after k
+    # steps n_i(r) is the old n_i(r - k c_i), bit for bit
+    pops = lat.populations()
+    want = {k: torch.stack([pops[i, (idx[:, 2] - k * int(c[i, 2])) % L, (idx[:, 1] - k * int(c[i, 1])) % L,
+                                 (idx[:, 0] - k * int(c[i, 0])) % L] for i in range(19)]) for k in (1, 2)}
+    del pops
+    torch.cuda.empty_cache()
+    for k in (1, 2):
+        say(f"  propagate, t = {lat.t}")
+        lat.propagate(1)
+        pops = lat.populations()
+        got = pops[:, idx[:, 2], idx[:, 1], idx[:, 0]]
+        del pops
+        torch.cuda.empty_cache()
+        assert torch.equal(got, want[k]), k
     lat.close()
 
 
