@@ -99,6 +99,7 @@ def test_other_argument_errors():
     assert L.lb_init(ctypes.byref(p), ctypes.c_void_p(256), None, 2, None, 0, ctypes.byref(ctx)) == lb.LB_EINVAL
     assert L.lb_init(ctypes.byref(p), ctypes.c_void_p(256), None, 0, None, -1, ctypes.byref(ctx)) == lb.LB_EINVAL
     assert L.lb_step(None, 1) == lb.LB_EINVAL
+    assert L.lb_propagate(None, 1) == lb.LB_EINVAL
     assert L.lb_moments(None, None) == lb.LB_EINVAL
     assert L.lb_step_count(None) == -1
     L.lb_destroy(None)
