@@ -461,13 +461,15 @@ int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity
   return LB_OK;
 }
 
-// Default schedule, from measurements on MI355X (512^3 box): fp32 runs the
-// even step row-tiled and the odd step flat, both without XCD remapping; the
-// 16-bit forms run the even step flat and the odd step row-tiled, both with
-// XCD groups of 8 consecutive tiles.  lb_autotune refines it for a given
-// workload.
+// Default schedule, from measurements on MI355X (512^3 D3Q19 and 16384^2
+// D2Q9 boxes): fp32 runs the even step row-tiled and the odd step flat, both
+// without XCD remapping; the 16-bit forms run the even step flat and the odd
+// step row-tiled, with XCD groups of 8 consecutive tiles on D3Q19 and no
+// remapping on D2Q9 (groups of 8 made the D2Q9 bf16 step 10% slower).
+// lb_autotune refines it for a given workload.
 int default_schedule(lb_ctx* c) {
   if (c->storage == LB_F32) c->sched = lb_schedule{256, 0, 16, {0, 0}, {1, 0}};
+  else if (c->lattice == LB_D2Q9) c->sched = lb_schedule{256, 0, 16, {0, 0}, {0, 1}};
   else c->sched = lb_schedule{256, 0, 16, {8, 8}, {0, 1}};
   if (c->wide) c->sched.tiling[0] = c->sched.tiling[1] = 0;
   return upload_schedule(c);
