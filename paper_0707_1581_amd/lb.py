@@ -135,6 +135,17 @@ def _stream_ptr(device, stream):
     return ctypes.c_void_p(s.cuda_stream), s
 
 
+def _adopt(t, device, lat_stream):
+    """Order the library's work on lat_stream after the caller's current
+    stream (which may have just produced or recycled t's memory), and keep
+    the caching allocator from reusing t's memory before lat_stream is done
+    with it."""
+    cur = torch.cuda.current_stream(device)
+    if lat_stream != cur:
+        lat_stream.wait_stream(cur)
+        t.record_stream(lat_stream)
+
+
 def _aligned(t):
     if t.data_ptr() % 256:
         raise ValueError("device buffers must be 256-byte aligned")
@@ -155,21 +166,27 @@ class _Gathers:
     def dim(self):
         return LATTICE_QD[self.lattice][1]
 
-    def populations(self):
-        out = torch.empty((self.q, *self._dims()), dtype=torch.float32, device=self.device)
-        _check(lib().lb_populations(self._ctx, _aligned(out)), "lb_populations")
+    def _gather(self, fn, name, rows):
+        """Run a gather on the lattice's stream into a new tensor that the
+        caller's current stream may use at once."""
+        lat_stream = self.stream if isinstance(self, Lattice) else self._ens.stream
+        out = torch.empty((rows, *self._dims()), dtype=torch.float32, device=self.device)
+        _adopt(out, self.device, lat_stream)
+        _check(fn(self._ctx, _aligned(out)), name)
+        cur = torch.cuda.current_stream(self.device)
+        if lat_stream != cur:
+            cur.wait_stream(lat_stream)
         return out
+
+    def populations(self):
+        return self._gather(lib().lb_populations, "lb_populations", self.q)
 
     def moments(self):
         """(1 + d, nz, ny, nx): rho, jx, jy[, jz]."""
-        out = torch.empty((1 + self.dim, *self._dims()), dtype=torch.float32, device=self.device)
-        _check(lib().lb_moments(self._ctx, _aligned(out)), "lb_moments")
-        return out
+        return self._gather(lib().lb_moments, "lb_moments", 1 + self.dim)
 
     def modes(self):
-        out = torch.empty((self.q, *self._dims()), dtype=torch.float32, device=self.device)
-        _check(lib().lb_modes(self._ctx, _aligned(out)), "lb_modes")
-        return out
+        return self._gather(lib().lb_modes, "lb_modes", self.q)
 
     def check(self):
         """(n_bad, [sum rho, sum jx, sum jy, sum jz]); raises on LB_ESTATE."""
@@ -219,6 +236,9 @@ class Lattice(_Gathers):
                 raise ValueError(f"fields must be {fshape}")
             f = _aligned(self._fields)
         sp, self.stream = _stream_ptr(self.device, stream)
+        _adopt(self.state, self.device, self.stream)
+        if f is not None:
+            _adopt(self._fields, self.device, self.stream)
         ctx = ctypes.c_void_p()
         _check(lib().lb_init(ctypes.byref(self.params), _aligned(self.state), sp, INIT[init], f,
                              int(t0), ctypes.byref(ctx)), "lb_init")
@@ -298,6 +318,7 @@ class Ensemble:
             raise LBError(LB_EINVAL, "lb_batch_pool_bytes")
         self.pool = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         sp, self.stream = _stream_ptr(self.device, stream)
+        _adopt(self.pool, self.device, self.stream)
         ctx = ctypes.c_void_p()
         _check(lib().lb_batch_init(self._arr, n, _aligned(self.pool), sp, INIT[init], int(t0),
                                    ctypes.byref(ctx)), "lb_batch_init")

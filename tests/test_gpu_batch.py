@@ -141,17 +141,23 @@ def test_contexts_on_separate_streams():
     run one after the other on the default stream."""
     cfgs = [dict(nx=40, ny=12, nz=10, kT=1e-4, gamma_shear=0.6, seed=101),
             dict(nx=24, ny=24, nz=1, kT=5e-4, gamma_shear=0.3, seed=102, lattice="d2q9")]
-    ref = []
+    ref, ref_pops = [], []
     for c in cfgs:
         lat = lbf.Lattice(**c, init="thermal")
         lat.step(41)
         ref.append(lat.state.clone())
+        ref_pops.append(lat.populations())
         lat.close()
     streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     lats = [lbf.Lattice(**c, init="thermal", stream=s) for c, s in zip(cfgs, streams)]
     for k in range(41):
         lats[k % 2].step(1)
         lats[(k + 1) % 2].step(1)
+    # gathers run on each lattice's stream behind its queued steps, and the
+    # caller's stream may use their results at once, without a synchronize
+    got = [lat.populations().clone() for lat in lats]
+    for g, want in zip(got, ref_pops):
+        assert torch.equal(g, want)
     torch.cuda.synchronize()
     for lat, want in zip(lats, ref):
         assert lat.t == 41
