@@ -784,7 +784,11 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   char* scratch = nullptr;
   HIP_TRY(hipMalloc(&scratch, bytes));
   const uint64_t base0 = ctx->lats[0].base - ctx->offsets[0];
-  HIP_TRY(hipMemcpyAsync(scratch, (void*)(uintptr_t)base0, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+  const hipError_t ce = hipMemcpyAsync(scratch, (void*)(uintptr_t)base0, bytes, hipMemcpyDeviceToDevice, ctx->stream);
+  if (ce != hipSuccess) {
+    (void)hipFree(scratch);
+    return fail(LB_EDEVICE, std::string("hipMemcpyAsync (autotune scratch copy): ") + hipGetErrorString(ce));
+  }
 
   const std::vector<LatDesc> saved_lats = ctx->lats;
   const lb_schedule saved = ctx->sched;
