@@ -53,8 +53,10 @@
  *   - the stream is the caller's hipStream_t passed as void*; every kernel
  *     of a context runs on it; only lb_check and lb_autotune synchronise;
  *   - argument errors are detected before anything is enqueued (nothing is
- *     done); launch failures return LB_EDEVICE; lb_last_error() gives the
- *     message of the last failure on the calling thread;
+ *     done); launch failures return LB_EDEVICE, after which the state and
+ *     step count of that context are undefined (some of the requested steps
+ *     may have run); lb_last_error() gives the message of the last failure
+ *     on the calling thread;
  *   - a context is not thread-safe; separate contexts are independent.
  */
 #ifndef LBF_H
