@@ -430,10 +430,16 @@ def main():
                 "kernel": "fp32 step kernel (lbf::k_step / lbf::k_step_rows as scheduled; even and odd "
                           "AA launches; mean launch duration)",
                 "alg_bytes_per_launch": main_run["alg_bytes_per_launch"]}
-    # the data-movement floor of the timed step: the same launches without the
-    # collision (lb_propagate, same schedule, accesses and cache policy)
+    # two references for the step's HBM rate, measured on this device: the
+    # library's float4 non-temporal copy (the practical streaming ceiling) and
+    # the same launches as the timed step without the collision (lb_propagate,
+    # same schedule, accesses and cache policy)
+    from paper_0707_1581_amd import lb as lbmod
+    copy_gbs = lbmod.copy_rate(gib=4, reps=10)
     prop = main_run["propagate_only"]
-    ceilings = {"propagate_only_ms_per_step": prop["ms_per_step"], "propagate_only_gbs": prop["achieved_gbs"],
+    ceilings = {"device_copy_gbs": copy_gbs, "device_copy_frac_of_peak": copy_gbs / HBM_PEAK_GBS,
+                "step_frac_of_device_copy": main_run["achieved_gbs"] / copy_gbs,
+                "propagate_only_ms_per_step": prop["ms_per_step"], "propagate_only_gbs": prop["achieved_gbs"],
                 "propagate_only_frac_of_peak": prop["achieved_gbs"] / HBM_PEAK_GBS,
                 "step_speed_frac_of_propagate_only": prop["ms_per_step"] / main_run["ms_per_step"]}
     line = {

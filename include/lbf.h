@@ -51,7 +51,8 @@
  *   - device pointers (d_*) are caller-owned, contiguous, 256-byte aligned
  *     device memory; the library never frees them;
  *   - the stream is the caller's hipStream_t passed as void*; every kernel
- *     of a context runs on it; only lb_check and lb_autotune synchronise;
+ *     of a context runs on it; only lb_check, lb_autotune and lb_copy_rate
+ *     synchronise;
  *   - argument errors are detected before anything is enqueued (nothing is
  *     done); launch failures return LB_EDEVICE, after which the state and
  *     step count of that context are undefined (some of the requested steps
@@ -246,6 +247,18 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
  * refined_odd_ms for the re-timed ones) into report (NUL-terminated,
  * truncated to report_len).  Allocates a scratch copy of the state. */
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
+
+/* ---- calibration ---- */
+
+/* The practical streaming ceiling of the device: copies `bytes` (a positive
+ * multiple of 16) from d_src to d_dst (caller-owned, 256-byte aligned,
+ * non-overlapping device buffers) with one float4 per lane and
+ * non-temporal loads and stores, once as a warm-up and then `reps` >= 1
+ * times on the given stream, timed with HIP events, and writes the rate
+ * counting bytes read plus bytes written, in GB/s, to *gbs_out.
+ * Synchronises the stream.  Not part of the method: a reference against
+ * which the step kernels' HBM rate is read. */
+int lb_copy_rate(const void* d_src, void* d_dst, size_t bytes, int32_t reps, void* hip_stream, double* gbs_out);
 
 #ifdef __cplusplus
 }

@@ -113,6 +113,16 @@ LatDesc make_desc(const lb_params& p, uint64_t base) {
 // 32-bit size).
 bool is_wide(const lb_params& p) { return sites_of(p) * elem_size(p.storage) >= (1ull << 32); }
 
+// ---------------------------------------------------------------- copy calibration
+// The practical streaming ceiling: one float4 per lane, non-temporal load
+// and store (the fastest plain copy form measured on MI355X).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_copy4(const f32x4* __restrict__ src, f32x4* __restrict__ dst, uint64_t n4) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i < n4)
+    __builtin_nontemporal_store(__builtin_nontemporal_load((const LBF_GLOBAL f32x4*)src + i), (LBF_GLOBAL f32x4*)dst + i);
+}
+
 // ---------------------------------------------------------------- kernel tables
 // Step kernels (PROP = false) and their propagation-only twins (PROP = true),
 // flat tiling.
@@ -626,6 +636,41 @@ void lb_destroy(lb_ctx* ctx) {
   if (!ctx) return;
   if (ctx->owner) (void)hipStreamSynchronize(ctx->stream);
   free_ctx(ctx);
+}
+
+int lb_copy_rate(const void* d_src, void* d_dst, size_t bytes, int32_t reps, void* hip_stream, double* gbs_out) {
+  if (!d_src || !d_dst || !gbs_out) return fail(LB_EINVAL, "NULL argument");
+  if (((uintptr_t)d_src & 255) || ((uintptr_t)d_dst & 255)) return fail(LB_EINVAL, "buffers must be 256-byte aligned");
+  if (bytes == 0 || bytes % 16) return fail(LB_EINVAL, "bytes must be a positive multiple of 16");
+  const uint64_t n4 = bytes / 16;
+  if ((n4 + 255) / 256 > 0x7FFFFFFFull) return fail(LB_EUNSUPPORTED, "copy too large for one launch");
+  if (reps < 1) return fail(LB_EINVAL, "reps must be >= 1");
+  const char* s = (const char*)d_src;
+  const char* d = (const char*)d_dst;
+  if (s < d + bytes && d < s + bytes) return fail(LB_EINVAL, "source and destination overlap");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const dim3 grid((uint32_t)((n4 + 255) / 256));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_copy4, grid, dim3(256), 0, st, (const f32x4*)d_src, (f32x4*)d_dst, n4);  // warm-up
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    hipLaunchKernelGGL(k_copy4, grid, dim3(256), 0, st, (const f32x4*)d_src, (f32x4*)d_dst, n4);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(LB_EDEVICE, std::string("lb_copy_rate: ") + hipGetErrorString(e));
+  *gbs_out = 2.0 * (double)bytes * reps / ((double)ms * 1e6);
+  return LB_OK;
 }
 
 int lb_params_from_physical(double b, double h, double rho, double eta, double zeta, double kBT,

@@ -80,6 +80,7 @@ SIGNATURES = [
     ("lb_get_schedule", ctypes.c_int, [_vp, _P(LbSchedule)]),
     ("lb_set_schedule", ctypes.c_int, [_vp, _P(LbSchedule)]),
     ("lb_autotune", ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
+    ("lb_copy_rate", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int32, _vp, _P(ctypes.c_double)]),
 ]
 
 _lib = None
@@ -128,6 +129,22 @@ def physical_params(b, h, rho, eta, zeta, kBT, lattice="d3q19"):
     _check(lib().lb_params_from_physical(b, h, rho, eta, zeta, kBT, ctypes.byref(p)),
            "lb_params_from_physical")
     return dict(rho0=p.rho0, kT=p.kT, gamma_shear=p.gamma_shear, gamma_bulk=p.gamma_bulk)
+
+
+def copy_rate(gib=4, reps=10, device="cuda", stream=None):
+    """GB/s (read + write) of the library's float4 non-temporal device copy
+    of two gib-GiB buffers: the practical streaming ceiling."""
+    dev = torch.device(device)
+    n = int(gib * (1 << 30)) // 16 * 16
+    src = torch.ones(n // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    sp, s = _stream_ptr(dev, stream)
+    _adopt(src, dev, s)
+    _adopt(dst, dev, s)
+    out = ctypes.c_double(0.0)
+    _check(lib().lb_copy_rate(_aligned(src), _aligned(dst), n, int(reps), sp, ctypes.byref(out)), "lb_copy_rate")
+    del src, dst
+    return out.value
 
 
 def _stream_ptr(device, stream):

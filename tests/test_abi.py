@@ -100,6 +100,16 @@ def test_other_argument_errors():
     assert L.lb_init(ctypes.byref(p), ctypes.c_void_p(256), None, 0, None, -1, ctypes.byref(ctx)) == lb.LB_EINVAL
     assert L.lb_step(None, 1) == lb.LB_EINVAL
     assert L.lb_propagate(None, 1) == lb.LB_EINVAL
+    # copy calibration: argument errors are caught before any device call
+    out = ctypes.c_double(0.0)
+    a, b = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+    assert L.lb_copy_rate(None, b, 1024, 1, None, ctypes.byref(out)) == lb.LB_EINVAL
+    assert L.lb_copy_rate(a, b, 1024, 1, None, None) == lb.LB_EINVAL
+    assert L.lb_copy_rate(ctypes.c_void_p((1 << 20) + 16), b, 1024, 1, None, ctypes.byref(out)) == lb.LB_EINVAL
+    assert L.lb_copy_rate(a, b, 1000, 1, None, ctypes.byref(out)) == lb.LB_EINVAL
+    assert L.lb_copy_rate(a, b, 0, 1, None, ctypes.byref(out)) == lb.LB_EINVAL
+    assert L.lb_copy_rate(a, b, 1024, 0, None, ctypes.byref(out)) == lb.LB_EINVAL
+    assert L.lb_copy_rate(a, ctypes.c_void_p((1 << 20) + 512), 1024, 1, None, ctypes.byref(out)) == lb.LB_EINVAL
     assert L.lb_moments(None, None) == lb.LB_EINVAL
     assert L.lb_step_count(None) == -1
     L.lb_destroy(None)

@@ -3,6 +3,8 @@ identity collision moves every population n_i from r to r + c_i, periodic,
 so the state after k such steps is the initial one with each population
 field rolled by k c_i, bit for bit, on both lattices, in every storage form,
 from either AA parity, for single lattices and batches."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -119,3 +121,20 @@ def test_stream_argument_errors():
     assert lb.lib().lb_propagate(ens.view(1)._ctx, 1) == lb.LB_EINVAL   # views cannot move; their batch can
     assert ens.t == 0
     ens.close()
+
+
+def test_copy_rate_copies_and_reports_a_rate():
+    """The copy calibration moves the bytes exactly and reports a positive
+    rate below the HBM peak (read + write counted)."""
+    n = (64 << 20) // 4
+    src = torch.arange(n, dtype=torch.float32, device="cuda")
+    dst = torch.zeros_like(src)
+    out = ctypes.c_double(0.0)
+    rc = lb.lib().lb_copy_rate(lb._aligned(src), lb._aligned(dst), 4 * n, 3,
+                               torch.cuda.current_stream().cuda_stream, ctypes.byref(out))
+    assert rc == lb.LB_OK
+    assert torch.equal(src, dst)
+    assert 0.0 < out.value < 8000.0 * 1.05
+    rate = lb.copy_rate(gib=1, reps=3)
+    say(f"device copy, 1 GiB: {rate:.0f} GB/s")
+    assert 1000.0 < rate < 8000.0 * 1.05
