@@ -198,8 +198,17 @@ def run_ensemble(storage, steps, warmup):
     ens.autotune(steps=10)
     ms = time_steps(ens.step, steps, warmup, ens.stream)
     sites = ens.sites()
+    import inspect
+    meta_seed = inspect.signature(workloads.ensemble_replicas).parameters["meta_seed"].default
+    sizes = {}
+    for r in reps:
+        sizes[f"{r['nx']}^3"] = sizes.get(f"{r['nx']}^3", 0) + 1
     out = dict(storage=storage, replicas=len(reps), sites=sites, ms_per_step=ms,
-               mlups=sites / ms / 1e3, schedule=ens.schedule())
+               mlups=sites / ms / 1e3, schedule=ens.schedule(),
+               workload={"meta_seed": meta_seed, "boxes": sizes,
+                         "kT": [min(r["kT"] for r in reps), max(r["kT"] for r in reps)],
+                         "gamma_shear": [min(r["gamma_shear"] for r in reps), max(r["gamma_shear"] for r in reps)],
+                         "steps": steps})
     pooled, per = ensemble_mode_variances(ens, reps)
     out["mode_variance_max_dev"] = max(abs(x - 1.0) for x in pooled)
     out["mode_variance_max_dev_per_replica"] = max(abs(x - 1.0) for rr in per for x in rr)
