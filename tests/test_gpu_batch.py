@@ -214,3 +214,30 @@ def test_batch_rest_init_and_keep(lattice):
     for r in range(len(reps)):
         assert torch.equal(ens2.replica_state(r), want[r]), r
     ens2.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_many_small_uneven_replicas(storage):
+    """257 replicas of uneven shapes from 1 x 1 x 1 to 9 x 9 x 9 (the
+    binary search over the tile prefix, partial tiles, rows shorter than a
+    segment, tile orders): sampled replicas are bit-identical to their
+    standalone runs under flat and row tilings."""
+    rng = np.random.default_rng(11)
+    reps = []
+    for r in range(257):
+        nx, ny, nz = (int(v) for v in rng.integers(1, 10, 3))
+        reps.append(dict(nx=nx, ny=ny, nz=nz, rho0=1.0, kT=float(rng.uniform(1e-5, 1e-3)), gamma_bulk=0.5,
+                         gamma_shear=float(rng.uniform(0, 0.9)), gamma_odd=0.0, gamma_even=0.0, seed=1000 + r))
+    reps[0] = dict(reps[0], nx=1, ny=1, nz=1)
+    sample = [0, 1, 128, 200, 256]
+    want = {r: standalone_states([reps[r]], storage, 7)[0] for r in sample}
+    for sched in [dict(block=64, order=1, xcd_remap=1, graph_chunk=4, tiling=0),
+                  dict(block=128, order=2, xcd_remap=(0, 8), graph_chunk=2, tiling=(1, 0)),
+                  dict(block=512, order=0, xcd_remap=2, graph_chunk=16, tiling=1)]:
+        ens = lbf.Ensemble(reps, storage=storage, init="thermal")
+        ens.set_schedule(**sched)
+        ens.step(7)
+        for r in sample:
+            assert torch.equal(ens.replica_state(r), want[r]), (sched, r)
+        assert ens.view(128).check()[0] == 0
+        ens.close()
