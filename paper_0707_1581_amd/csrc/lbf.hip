@@ -738,11 +738,12 @@ int lb_batch_init(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_s
   c->storage = reps[0].storage;
   c->lattice = reps[0].lattice;
   c->wide = false;
+  uint64_t off = 0;  // running lb_batch_offset
   for (int r = 0; r < nrep; ++r) {
-    const uint64_t off = lb_batch_offset(reps, nrep, r);
     c->reps.push_back(reps[r]);
     c->offsets.push_back(off);
     c->lats.push_back(make_desc(reps[r], (uint64_t)(uintptr_t)d_pool + off));
+    off += (lb_state_bytes(&reps[r]) + 255) & ~(size_t)255;
   }
   c->t = t0;
   int rc;
