@@ -75,7 +75,7 @@ enum lb_status {
   LB_EINVAL = -1,       /* invalid argument; nothing enqueued            */
   LB_EDEVICE = -2,      /* HIP runtime or launch failure                 */
   LB_ESTATE = -3,       /* lb_check found NaN or rho <= 0 sites          */
-  LB_EUNSUPPORTED = -4  /* valid request this build does not provide     */
+  LB_EUNSUPPORTED = -4  /* valid request the library does not provide   */
 };
 
 enum lb_storage { LB_F32 = 0, LB_F16 = 1, LB_BF16 = 2 };

@@ -2,7 +2,7 @@
 
 The library holds the HIP kernels and the C ABI declared in
 ``include/lbf.h``; it is built in-tree, next to this file, so that the
-Python binding loads exactly this build.
+Python binding loads the library compiled from these sources.
 """
 import os
 import subprocess
