@@ -207,7 +207,8 @@ int lb_batch_init(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_s
                   int32_t init_kind, int64_t t0, lb_ctx** out);
 
 /* Advance every replica by nsteps; one kernel launch per step covers all
- * replicas, and full chunks of steps are replayed from a HIP graph. */
+ * replicas (one per replica group when the schedule's group_mb is set), and
+ * full chunks of steps are replayed from a HIP graph. */
 int lb_batch_step(lb_ctx* batch, int64_t nsteps);
 
 /* A non-owning context for replica r (gathers and lb_check only; its step
@@ -230,6 +231,18 @@ typedef struct {
                         /* `block`-long segment of one x-row, so y/z offsets   */
                         /* are uniform (planes below 4 GiB, else               */
                         /* LB_EUNSUPPORTED)                                    */
+  int32_t resident;     /* cache policy of the step kernels: 0 streaming (non- */
+                        /* temporal accesses, except the odd step's x-shifted  */
+                        /* planes); 1 every access cached, for state that      */
+                        /* stays in the 256 MB Infinity Cache across launches  */
+                        /* (planes below 4 GiB, else LB_EUNSUPPORTED)          */
+  int32_t group_mb;     /* 0: every step is one launch over all lattices; g > 0 */
+                        /* (up to 2^20): lattices in tile order are packed into */
+                        /* groups of at most g MiB of state (a larger lattice  */
+                        /* is a group of its own), each step launches once per */
+                        /* group, and a graph replay runs all graph_chunk      */
+                        /* steps of one group before the next.  Replicas are   */
+                        /* independent, so results do not depend on it.        */
 } lb_schedule;
 
 int lb_get_schedule(const lb_ctx* ctx, lb_schedule* out);
@@ -238,13 +251,19 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
 /* Time every candidate schedule on a scratch copy of the state (the state
  * and step count of ctx are unchanged): every block size and tile order
  * with every (xcd_remap in {0, 1, 2, 4, 8}, tiling) pair, timed on even and
- * on odd steps separately (`steps` >= 2 launches of each parity).  The six
- * fastest candidates of each parity are then timed again in three
- * interleaved rounds, and the choice rests on those times: the block size
- * and order whose fastest even and odd (remap, tiling) choices sum lowest.
- * Applies the best schedule and writes a JSON report (one object per
- * candidate with its mean even and odd step times, plus refined_even_ms /
- * refined_odd_ms for the re-timed ones) into report (NUL-terminated,
+ * on odd steps separately (`steps` >= 2 launches of each parity), with the
+ * streaming cache policy and one group.  The six fastest candidates of each
+ * parity are then timed again in three interleaved rounds, and the choice
+ * rests on those times: the block size and order whose fastest even and
+ * odd (remap, tiling) choices sum lowest.  A second stage times that
+ * schedule on whole graph replays (at least 2 * `steps` steps, three
+ * interleaved rounds) with each cache policy and, for a batch, replica
+ * groups of 0, 64, 128, 160, 192 and 224 MiB, and keeps a variant only if
+ * it is at least 1% faster than the first stage's choice.  Applies the best
+ * schedule and writes a JSON report (one object per first-stage candidate with its
+ * mean even and odd step times, plus refined_even_ms / refined_odd_ms for
+ * the re-timed ones; then one object per second-stage variant with its
+ * resident, group_mb and ms_per_step) into report (NUL-terminated,
  * truncated to report_len).  Allocates a scratch copy of the state. */
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
 

@@ -125,66 +125,76 @@ __global__ void __launch_bounds__(256) k_copy4(const f32x4* __restrict__ src, f3
 
 // ---------------------------------------------------------------- kernel tables
 // Step kernels (PROP = false) and their propagation-only twins (PROP = true),
-// flat tiling.
-template <class M, int S, int P, bool W, bool PROP>
+// flat tiling, with the streaming or (RES) the resident cache policy; the
+// resident kernels exist for planes below 4 GiB only.
+template <class M, int S, int P, bool W, bool PROP, bool RES>
 void* step_ptr_b(int block) {
   switch (block) {
-    case 64: return PROP ? (void*)&k_propagate<M, S, P, W, 64> : (void*)&k_step<M, S, P, W, 64>;
-    case 128: return PROP ? (void*)&k_propagate<M, S, P, W, 128> : (void*)&k_step<M, S, P, W, 128>;
-    case 256: return PROP ? (void*)&k_propagate<M, S, P, W, 256> : (void*)&k_step<M, S, P, W, 256>;
-    case 512: return PROP ? (void*)&k_propagate<M, S, P, W, 512> : (void*)&k_step<M, S, P, W, 512>;
+    case 64: return PROP ? (void*)&k_propagate<M, S, P, W, 64, RES> : (void*)&k_step<M, S, P, W, 64, RES>;
+    case 128: return PROP ? (void*)&k_propagate<M, S, P, W, 128, RES> : (void*)&k_step<M, S, P, W, 128, RES>;
+    case 256: return PROP ? (void*)&k_propagate<M, S, P, W, 256, RES> : (void*)&k_step<M, S, P, W, 256, RES>;
+    case 512: return PROP ? (void*)&k_propagate<M, S, P, W, 512, RES> : (void*)&k_step<M, S, P, W, 512, RES>;
+  }
+  return nullptr;
+}
+template <class M, int S, int P, bool PROP>
+void* step_ptr_p(bool wide, bool res, int block) {
+  if (wide) return res ? nullptr : step_ptr_b<M, S, P, true, PROP, false>(block);
+  return res ? step_ptr_b<M, S, P, false, PROP, true>(block) : step_ptr_b<M, S, P, false, PROP, false>(block);
+}
+template <class M, int S, bool PROP>
+void* step_ptr_s(int parity, bool wide, bool res, int block) {
+  return parity ? step_ptr_p<M, S, 1, PROP>(wide, res, block) : step_ptr_p<M, S, 0, PROP>(wide, res, block);
+}
+template <class M, bool PROP>
+void* step_ptr_m(int storage, int parity, bool wide, bool res, int block) {
+  switch (storage) {
+    case LB_F32: return step_ptr_s<M, ST_F32, PROP>(parity, wide, res, block);
+    case LB_F16: return step_ptr_s<M, ST_F16, PROP>(parity, wide, res, block);
+    case LB_BF16: return step_ptr_s<M, ST_BF16, PROP>(parity, wide, res, block);
+  }
+  return nullptr;
+}
+void* step_ptr(int lattice, int storage, int parity, bool wide, bool res, int block, bool prop) {
+  if (prop)
+    return lattice == LB_D2Q9 ? step_ptr_m<D2Q9, true>(storage, parity, wide, res, block)
+                              : step_ptr_m<D3Q19, true>(storage, parity, wide, res, block);
+  return lattice == LB_D2Q9 ? step_ptr_m<D2Q9, false>(storage, parity, wide, res, block)
+                            : step_ptr_m<D3Q19, false>(storage, parity, wide, res, block);
+}
+
+// Row-tiled step kernels and their propagation-only twins (non-wide
+// lattices only), both cache policies.
+template <class M, int S, int P, bool PROP, bool RES>
+void* rows_ptr_b(int block) {
+  switch (block) {
+    case 64: return PROP ? (void*)&k_propagate_rows<M, S, P, 64, RES> : (void*)&k_step_rows<M, S, P, 64, RES>;
+    case 128: return PROP ? (void*)&k_propagate_rows<M, S, P, 128, RES> : (void*)&k_step_rows<M, S, P, 128, RES>;
+    case 256: return PROP ? (void*)&k_propagate_rows<M, S, P, 256, RES> : (void*)&k_step_rows<M, S, P, 256, RES>;
+    case 512: return PROP ? (void*)&k_propagate_rows<M, S, P, 512, RES> : (void*)&k_step_rows<M, S, P, 512, RES>;
   }
   return nullptr;
 }
 template <class M, int S, bool PROP>
-void* step_ptr_s(int parity, bool wide, int block) {
-  if (parity) return wide ? step_ptr_b<M, S, 1, true, PROP>(block) : step_ptr_b<M, S, 1, false, PROP>(block);
-  return wide ? step_ptr_b<M, S, 0, true, PROP>(block) : step_ptr_b<M, S, 0, false, PROP>(block);
+void* rows_ptr_s(int parity, bool res, int block) {
+  if (parity) return res ? rows_ptr_b<M, S, 1, PROP, true>(block) : rows_ptr_b<M, S, 1, PROP, false>(block);
+  return res ? rows_ptr_b<M, S, 0, PROP, true>(block) : rows_ptr_b<M, S, 0, PROP, false>(block);
 }
 template <class M, bool PROP>
-void* step_ptr_m(int storage, int parity, bool wide, int block) {
+void* rows_ptr_m(int storage, int parity, bool res, int block) {
   switch (storage) {
-    case LB_F32: return step_ptr_s<M, ST_F32, PROP>(parity, wide, block);
-    case LB_F16: return step_ptr_s<M, ST_F16, PROP>(parity, wide, block);
-    case LB_BF16: return step_ptr_s<M, ST_BF16, PROP>(parity, wide, block);
+    case LB_F32: return rows_ptr_s<M, ST_F32, PROP>(parity, res, block);
+    case LB_F16: return rows_ptr_s<M, ST_F16, PROP>(parity, res, block);
+    case LB_BF16: return rows_ptr_s<M, ST_BF16, PROP>(parity, res, block);
   }
   return nullptr;
 }
-void* step_ptr(int lattice, int storage, int parity, bool wide, int block, bool prop) {
+void* rows_ptr(int lattice, int storage, int parity, bool res, int block, bool prop) {
   if (prop)
-    return lattice == LB_D2Q9 ? step_ptr_m<D2Q9, true>(storage, parity, wide, block)
-                              : step_ptr_m<D3Q19, true>(storage, parity, wide, block);
-  return lattice == LB_D2Q9 ? step_ptr_m<D2Q9, false>(storage, parity, wide, block)
-                            : step_ptr_m<D3Q19, false>(storage, parity, wide, block);
-}
-
-// Row-tiled step kernels and their propagation-only twins (non-wide
-// lattices only).
-template <class M, int S, int P, bool PROP>
-void* rows_ptr_b(int block) {
-  switch (block) {
-    case 64: return PROP ? (void*)&k_propagate_rows<M, S, P, 64> : (void*)&k_step_rows<M, S, P, 64>;
-    case 128: return PROP ? (void*)&k_propagate_rows<M, S, P, 128> : (void*)&k_step_rows<M, S, P, 128>;
-    case 256: return PROP ? (void*)&k_propagate_rows<M, S, P, 256> : (void*)&k_step_rows<M, S, P, 256>;
-    case 512: return PROP ? (void*)&k_propagate_rows<M, S, P, 512> : (void*)&k_step_rows<M, S, P, 512>;
-  }
-  return nullptr;
-}
-template <class M, bool PROP>
-void* rows_ptr_m(int storage, int parity, int block) {
-  switch (storage) {
-    case LB_F32: return parity ? rows_ptr_b<M, ST_F32, 1, PROP>(block) : rows_ptr_b<M, ST_F32, 0, PROP>(block);
-    case LB_F16: return parity ? rows_ptr_b<M, ST_F16, 1, PROP>(block) : rows_ptr_b<M, ST_F16, 0, PROP>(block);
-    case LB_BF16: return parity ? rows_ptr_b<M, ST_BF16, 1, PROP>(block) : rows_ptr_b<M, ST_BF16, 0, PROP>(block);
-  }
-  return nullptr;
-}
-void* rows_ptr(int lattice, int storage, int parity, int block, bool prop) {
-  if (prop)
-    return lattice == LB_D2Q9 ? rows_ptr_m<D2Q9, true>(storage, parity, block)
-                              : rows_ptr_m<D3Q19, true>(storage, parity, block);
-  return lattice == LB_D2Q9 ? rows_ptr_m<D2Q9, false>(storage, parity, block)
-                            : rows_ptr_m<D3Q19, false>(storage, parity, block);
+    return lattice == LB_D2Q9 ? rows_ptr_m<D2Q9, true>(storage, parity, res, block)
+                              : rows_ptr_m<D3Q19, true>(storage, parity, res, block);
+  return lattice == LB_D2Q9 ? rows_ptr_m<D2Q9, false>(storage, parity, res, block)
+                            : rows_ptr_m<D3Q19, false>(storage, parity, res, block);
 }
 
 // Initial states (rest, thermal, fields), gathers (populations, moments,
@@ -255,9 +265,15 @@ struct lb_ctx {
   double* h_result = nullptr;   // pinned
   std::vector<LatDesc> lats;
 
-  lb_schedule sched{256, 0, 16, {0, 0}, {1, 0}};
-  uint32_t grid = 0;            // blocks per step
-  uint32_t grid_rows = 0;       // blocks per step with the row tiling
+  lb_schedule sched{256, 0, 16, {0, 0}, {1, 0}, 0, 0};
+  // Lattices in tile order are split into groups of consecutive lattices
+  // (one group unless sched.group_mb is set); every step is one launch per
+  // group, and a graph chunk runs all its steps on one group before the next.
+  struct Group {
+    uint32_t first, count;      // lattices [first, first + count) in tile order
+    uint32_t grid, grid_rows;   // workgroups per launch, flat and row tiling
+  };
+  std::vector<Group> groups;
 
   // graph of sched.graph_chunk steps starting at even t, plus the counter advance
   hipGraph_t graph = nullptr;
@@ -288,7 +304,8 @@ void drop_graph(lb_ctx* c) {
   c->graph = nullptr;
 }
 
-// Tile order and per-lattice block prefix for the current schedule.
+// Tile order, replica groups and the per-lattice block prefixes (relative to
+// the first tile of the lattice's group) for the current schedule.
 int upload_schedule(lb_ctx* c) {
   const int nlat = (int)c->lats.size();
   std::vector<int> order(nlat);
@@ -301,21 +318,35 @@ int upload_schedule(lb_ctx* c) {
                      [&](int a, int b) { return c->lats[a].nsites < c->lats[b].nsites; });
   std::vector<LatDesc> tl(nlat);
   std::vector<uint32_t> blk(nlat + 1), blk_rows(nlat + 1);
-  uint64_t acc = 0, acc_rows = 0;
+  std::vector<lb_ctx::Group> groups;
+  const uint64_t cap = (uint64_t)c->sched.group_mb << 20;  // state bytes per group; 0: one group
+  const uint64_t per_site = (uint64_t)q_of(c->lattice) * elem_size(c->storage);
+  uint64_t acc = 0, acc_rows = 0, bytes = 0;
+  uint32_t first = 0;
+  auto close_group = [&](uint32_t end) {
+    groups.push_back({first, end - first, (uint32_t)acc, (uint32_t)acc_rows});
+    return acc < (1ull << 31) && acc_rows < (1ull << 31);
+  };
   for (int i = 0; i < nlat; ++i) {
     tl[i] = c->lats[order[i]];
+    const uint64_t b = (per_site * tl[i].nsites + 255) & ~255ull;
+    if (cap && (uint32_t)i > first && bytes + b > cap) {  // a lattice above the cap is a group of its own
+      if (!close_group((uint32_t)i)) return fail(LB_EUNSUPPORTED, "too many workgroups for one launch");
+      first = (uint32_t)i;
+      acc = acc_rows = bytes = 0;
+    }
+    bytes += b;
     tl[i].segs = (tl[i].nx + c->sched.block - 1) / c->sched.block;
     div_magic(tl[i].segs, tl[i].ds_m, tl[i].ds_s1, tl[i].ds_s2);
     blk[i] = (uint32_t)acc;
     blk_rows[i] = (uint32_t)acc_rows;
-    acc += (c->lats[order[i]].nsites + c->sched.block - 1) / c->sched.block;
+    acc += (tl[i].nsites + c->sched.block - 1) / c->sched.block;
     acc_rows += (uint64_t)tl[i].ny * tl[i].nz * tl[i].segs;
   }
-  if (acc >= (1ull << 31) || acc_rows >= (1ull << 31)) return fail(LB_EUNSUPPORTED, "too many workgroups for one launch");
+  if (!close_group((uint32_t)nlat)) return fail(LB_EUNSUPPORTED, "too many workgroups for one launch");
   blk[nlat] = (uint32_t)acc;
   blk_rows[nlat] = (uint32_t)acc_rows;
-  c->grid = (uint32_t)acc;
-  c->grid_rows = (uint32_t)acc_rows;
+  c->groups = groups;
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(c->d_tile_lats, tl.data(), sizeof(LatDesc) * nlat, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_blk, blk.data(), sizeof(uint32_t) * (nlat + 1), hipMemcpyHostToDevice));
@@ -324,29 +355,36 @@ int upload_schedule(lb_ctx* c) {
   return LB_OK;
 }
 
-// Kernel, grid, workgroup size and tile prefix of a step of the given parity.
+// Kernel, grid, workgroup size, lattices and tile prefix of the launch of
+// group g in a step of the given parity.
 struct StepLaunch {
   void* fn;
   uint32_t grid;
   int block;
+  const LatDesc* lats;
   const uint32_t* blk;
+  uint32_t nlat;
 };
-StepLaunch step_launch(const lb_ctx* c, int parity, bool prop = false) {
+StepLaunch step_launch(const lb_ctx* c, int parity, size_t g, bool prop = false) {
+  const lb_ctx::Group& G = c->groups[g];
+  const bool res = c->sched.resident != 0;
   if (c->sched.tiling[parity])
-    return {rows_ptr(c->lattice, c->storage, parity, c->sched.block, prop), c->grid_rows, c->sched.block,
-            c->d_blk_rows};
-  return {step_ptr(c->lattice, c->storage, parity, c->wide, c->sched.block, prop), c->grid, c->sched.block,
-          c->d_blk};
+    return {rows_ptr(c->lattice, c->storage, parity, res, c->sched.block, prop), G.grid_rows, c->sched.block,
+            c->d_tile_lats + G.first, c->d_blk_rows + G.first, G.count};
+  return {step_ptr(c->lattice, c->storage, parity, c->wide, res, c->sched.block, prop), G.grid, c->sched.block,
+          c->d_tile_lats + G.first, c->d_blk + G.first, G.count};
 }
 
-// prop: the propagation-only kernel of the same schedule instead
+// One step of every group.  prop: the propagation-only kernels of the same
+// schedule instead.
 int launch_step(lb_ctx* c, uint32_t t_off, int parity, bool prop = false) {
-  const StepLaunch sl = step_launch(c, parity, prop);
-  if (!sl.fn) return fail(LB_EINVAL, "no step kernel for this schedule");
-  lb_ctx::StepArgs a{c->d_tile_lats, sl.blk, (uint32_t)c->lats.size(), (uint32_t)c->sched.xcd_remap[parity],
-                     c->d_t, t_off};
-  void* args[] = {&a.lats, &a.blk, &a.nlat, &a.remap, &a.d_t, &a.t_off};
-  HIP_TRY(hipLaunchKernel(sl.fn, dim3(sl.grid), dim3(sl.block), args, 0, c->stream));
+  for (size_t g = 0; g < c->groups.size(); ++g) {
+    const StepLaunch sl = step_launch(c, parity, g, prop);
+    if (!sl.fn) return fail(LB_EINVAL, "no step kernel for this schedule");
+    lb_ctx::StepArgs a{sl.lats, sl.blk, sl.nlat, (uint32_t)c->sched.xcd_remap[parity], c->d_t, t_off};
+    void* args[] = {&a.lats, &a.blk, &a.nlat, &a.remap, &a.d_t, &a.t_off};
+    HIP_TRY(hipLaunchKernel(sl.fn, dim3(sl.grid), dim3(sl.block), args, 0, c->stream));
+  }
   return LB_OK;
 }
 
@@ -356,18 +394,22 @@ int launch_advance(lb_ctx* c, uint64_t n) {
   return LB_OK;
 }
 
+// A chain of graph_chunk steps of each group in turn (all steps of one group
+// before the next, so a group whose state fits in the Infinity Cache stays
+// there), then the counter advance.
 int build_graph(lb_ctx* c) {
   drop_graph(c);
   const int K = c->sched.graph_chunk;
   HIP_TRY(hipGraphCreate(&c->graph, 0));
-  c->graph_args.assign(K, {});
+  c->graph_args.assign(K * c->groups.size(), {});
   hipGraphNode_t prev = nullptr;
-  for (int s = 0; s < K; ++s) {
-    const StepLaunch sl = step_launch(c, s & 1);
+  for (size_t n = 0; n < c->graph_args.size(); ++n) {
+    const size_t g = n / K;
+    const int s = (int)(n % K);
+    const StepLaunch sl = step_launch(c, s & 1, g);
     if (!sl.fn) return fail(LB_EINVAL, "no step kernel for this schedule");
-    c->graph_args[s] = {c->d_tile_lats, sl.blk, (uint32_t)c->lats.size(), (uint32_t)c->sched.xcd_remap[s & 1],
-                        c->d_t, (uint32_t)s};
-    lb_ctx::StepArgs& a = c->graph_args[s];
+    c->graph_args[n] = {sl.lats, sl.blk, sl.nlat, (uint32_t)c->sched.xcd_remap[s & 1], c->d_t, (uint32_t)s};
+    lb_ctx::StepArgs& a = c->graph_args[n];
     void* args[] = {&a.lats, &a.blk, &a.nlat, &a.remap, &a.d_t, &a.t_off};
     hipKernelNodeParams kp{};
     kp.func = sl.fn;
@@ -478,9 +520,9 @@ int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity
 // remapping on D2Q9 (groups of 8 made the D2Q9 bf16 step 10% slower).
 // lb_autotune refines it for a given workload.
 int default_schedule(lb_ctx* c) {
-  if (c->storage == LB_F32) c->sched = lb_schedule{256, 0, 16, {0, 0}, {1, 0}};
-  else if (c->lattice == LB_D2Q9) c->sched = lb_schedule{256, 0, 16, {0, 0}, {0, 1}};
-  else c->sched = lb_schedule{256, 0, 16, {8, 8}, {0, 1}};
+  if (c->storage == LB_F32) c->sched = lb_schedule{256, 0, 16, {0, 0}, {1, 0}, 0, 0};
+  else if (c->lattice == LB_D2Q9) c->sched = lb_schedule{256, 0, 16, {0, 0}, {0, 1}, 0, 0};
+  else c->sched = lb_schedule{256, 0, 16, {8, 8}, {0, 1}, 0, 0};
   if (c->wide) c->sched.tiling[0] = c->sched.tiling[1] = 0;
   return upload_schedule(c);
 }
@@ -810,6 +852,9 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s) {
   }
   if (s->graph_chunk < 2 || (s->graph_chunk & 1) || s->graph_chunk > 1024)
     return fail(LB_EINVAL, "graph_chunk must be even and in [2, 1024]");
+  if (s->resident != 0 && s->resident != 1) return fail(LB_EINVAL, "resident must be 0 or 1");
+  if (s->resident && ctx->wide) return fail(LB_EUNSUPPORTED, "the resident cache policy needs planes below 4 GiB");
+  if (s->group_mb < 0 || s->group_mb > (1 << 20)) return fail(LB_EINVAL, "group_mb must be in [0, 2^20]");
 
   HIP_TRY(hipSetDevice(ctx->device));
   ctx->sched = *s;
@@ -855,7 +900,7 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   // Mean even and odd step time of one schedule over `steps` launches of
   // each parity, after one warm-up launch of each.
   auto time_schedule = [&](const Cand& cd, double out[2]) -> int {
-    ctx->sched = lb_schedule{cd.block, cd.ord, saved.graph_chunk, {cd.remap, cd.remap}, {cd.til, cd.til}};
+    ctx->sched = lb_schedule{cd.block, cd.ord, saved.graph_chunk, {cd.remap, cd.remap}, {cd.til, cd.til}, 0, 0};
     int r = upload_schedule(ctx);
     if (r == LB_OK) r = direct_steps(ctx, 2);
     out[0] = out[1] = 0.0;
@@ -934,8 +979,59 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
     if (tot < best_ms) {
       best_ms = tot;
       best = lb_schedule{g.block, g.ord, saved.graph_chunk, {cands[pick[0]].remap, cands[pick[1]].remap},
-                         {cands[pick[0]].til, cands[pick[1]].til}};
+                         {cands[pick[0]].til, cands[pick[1]].til}, 0, 0};
     }
+  }
+
+  // Second stage: the cache policy and the replica groups of that schedule.
+  // Both pay only through reuse of cached state across the steps of a graph
+  // replay, so each variant is timed on whole replays (the path lb_step
+  // takes): one warm-up replay, then at least 2 * steps steps, in interleaved
+  // rounds.  A variant replaces the first stage's choice (streaming, one
+  // group) only when it is at least 1% faster.
+  struct Var {
+    int res, gmb;
+    double ms;
+  };
+  std::vector<Var> vars;
+  {
+    const int gmbs[] = {0, 64, 128, 160, 192, 224};
+    const int ngmb = ctx->lats.size() > 1 ? 6 : 1;
+    for (int res = 0; res < (ctx->wide ? 1 : 2); ++res)
+      for (int gi = 0; gi < ngmb; ++gi) vars.push_back({res, gmbs[gi], 0.0});
+  }
+  const int K2 = best.graph_chunk;
+  const int64_t chunks = std::max<int64_t>(1, (2 * (int64_t)steps + K2 - 1) / K2);
+  auto time_variant = [&](const Var& v, double& ms_out) -> int {
+    ctx->sched = best;
+    ctx->sched.resident = v.res;
+    ctx->sched.group_mb = v.gmb;
+    int r = upload_schedule(ctx);
+    if (r == LB_OK && (ctx->t & 1)) r = direct_steps(ctx, 1);
+    if (r == LB_OK) r = advance(ctx, K2);  // warm-up replay (builds the graph)
+    if (r != LB_OK) return r;
+    if (hipEventRecord(ev[0], ctx->stream) != hipSuccess) return fail(LB_EDEVICE, "hipEventRecord");
+    if ((r = advance(ctx, chunks * K2))) return r;
+    if (hipEventRecord(ev[1], ctx->stream) != hipSuccess) return fail(LB_EDEVICE, "hipEventRecord");
+    if (hipEventSynchronize(ev[1]) != hipSuccess) return fail(LB_EDEVICE, "hipEventSynchronize");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[0], ev[1]);
+    ms_out = ms / (double)(chunks * K2);
+    return LB_OK;
+  };
+  constexpr int ROUNDS2 = 3;
+  for (int round = 0; round < ROUNDS2 && rc == LB_OK && vars.size() > 1; ++round)
+    for (auto& v : vars) {
+      double ms = 0.0;
+      if ((rc = time_variant(v, ms))) break;
+      v.ms += ms / ROUNDS2;
+    }
+  if (rc == LB_OK && vars.size() > 1) {
+    const Var* pick = &vars[0];
+    for (const auto& v : vars)
+      if (v.ms < pick->ms && v.ms < 0.99 * vars[0].ms) pick = &v;
+    best.resident = pick->res;
+    best.group_mb = pick->gmb;
   }
 
   std::string rep = "[";
@@ -950,6 +1046,13 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
                     cd.ref[1]);
     else
       std::snprintf(buf + n, sizeof(buf) - n, "}");
+    rep += buf;
+  }
+  for (const auto& v : vars) {
+    if (vars.size() < 2 || rc != LB_OK) break;
+    char buf[160];
+    std::snprintf(buf, sizeof(buf), ",{\"stage\":2,\"resident\":%d,\"group_mb\":%d,\"ms_per_step\":%.6f}", v.res,
+                  v.gmb, v.ms);
     rep += buf;
   }
   rep += "]";

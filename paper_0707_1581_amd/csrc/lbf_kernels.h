@@ -172,15 +172,19 @@ __device__ __forceinline__ void neighbour_offsets(const LatDesc& L, uint32_t sit
 // of pure data movement; the odd step's x-shifted accesses share cache lines
 // between neighbouring waves, which non-temporal loads would evict early, so
 // it keeps those planes cached and streams the others.  The same policy
-// measured fastest for all three storage types.
+// measured fastest for all three storage types.  The resident policy (RES)
+// caches every access: it pays when the state a run of launches touches fits
+// in the 256 MB Infinity Cache (a small lattice, or one group of replicas
+// stepped several times before the next group), where streaming hints would
+// send every step back to HBM.
 #define LBF_GLOBAL __attribute__((address_space(1)))
 constexpr int CPOL_NT = 2;              // cache policy bit: non-temporal
 constexpr int RAW_BUFFER_WORD3 = 0x00020000;
 
-template <class M, int S, int P> struct CachePolicy {
+template <class M, int S, int P, bool RES = false> struct CachePolicy {
   // plane j of the odd step is accessed at r + c_j: shifted along x iff c_jx != 0
-  static constexpr bool nt_load(int j) { return P == 0 || M::CX[j] == 0; }
-  static constexpr bool nt_store(int j) { return P == 0 || M::CX[j] == 0; }
+  static constexpr bool nt_load(int j) { return !RES && (P == 0 || M::CX[j] == 0); }
+  static constexpr bool nt_store(int j) { return !RES && (P == 0 || M::CX[j] == 0); }
 };
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const LatDesc& L, int plane, uint32_t esize) {
@@ -304,10 +308,10 @@ __device__ __forceinline__ void st_pair16(LBF_GLOBAL char* pa, uint32_t ba, floa
 }
 
 // Load the q populations (as d_i) of site r of the state at parity P.
-template <class M, int S, int P, class Off>
+template <class M, int S, int P, bool RES = false, class Off>
 __device__ __forceinline__ void load_site(const LatDesc& L, uint32_t site, float d[M::Q], Off o[M::Q]) {
   using C = Codec<S>;
-  using CP = CachePolicy<M, S, P>;
+  using CP = CachePolicy<M, S, P, RES>;
   using T = typename C::T;
   if (P == 0) {
 #pragma unroll
@@ -414,8 +418,9 @@ __device__ __forceinline__ uint32_t find_lattice(const uint32_t* __restrict__ bl
 
 // ---------------------------------------------------------------- step kernel
 // One fused collide-and-stream step at step count t = *d_t + t_off with
-// parity P = t & 1, for every site of every lattice in lats[0..nlat).
-template <class M, int S, int P, bool WIDE, int BLOCK>
+// parity P = t & 1, for every site of every lattice in lats[0..nlat), with
+// the streaming or (RES) the resident cache policy.
+template <class M, int S, int P, bool WIDE, int BLOCK, bool RES>
 __global__ void __launch_bounds__(BLOCK)
 k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
        uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
@@ -433,9 +438,9 @@ k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint3
 
   float d[Q];
   Off o[Q];
-  load_site<M, S, P>(L, site, d, o);
+  load_site<M, S, P, RES>(L, site, d, o);
   collide<M>(L, d, site, (uint32_t)t, (uint32_t)(t >> 32));
-  using CP = CachePolicy<M, S, P>;
+  using CP = CachePolicy<M, S, P, RES>;
   using T = typename C::T;
   if constexpr (S != ST_F32 && !WIDE && P == 1) {
     // rest population alone, then the opposite pairs (i, i + 1), i odd, packed;
@@ -474,13 +479,14 @@ k_step(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint3
 // instruction as its scalar offset); each lane only computes x and its two
 // periodic x-neighbours.  Lanes past the end of the row stay idle, so this
 // suits rows of at least a few workgroups' worth of sites.
-template <class M, int S, int P, int BLOCK>
+template <class M, int S, int P, int BLOCK, bool RES>
 __global__ void __launch_bounds__(BLOCK)
 k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
             uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
   using C = Codec<S>;
   using T = typename C::T;
-  using CP = CachePolicy<M, S, 1>;
+  using CP = CachePolicy<M, S, P, RES>;
+  constexpr int EP = pol(CP::nt_load(0));  // the even step's one policy for every plane
   constexpr int Q = M::Q;
   constexpr uint32_t ES = sizeof(T);
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, remap);
@@ -515,7 +521,7 @@ k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
   if (P == 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      d[i] = C::dec(Raw<T>::template ld<CPOL_NT>(plane_rsrc(L, i, ES), bx, r0 * ES));
+      d[i] = C::dec(Raw<T>::template ld<EP>(plane_rsrc(L, i, ES), bx, r0 * ES));
   } else {
     // plane j at r + c_j holds population opp(j) of site r
 #pragma unroll
@@ -545,12 +551,12 @@ k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
   if constexpr (S != ST_F32) {
     // rest population alone, then the opposite pairs (i, i + 1), i odd, packed
     if (P == 0) {
-      Raw<T>::template st<CPOL_NT>(plane_rsrc(L, 0, ES), bx, C::enc(d[0]), r0 * ES);
+      Raw<T>::template st<EP>(plane_rsrc(L, 0, ES), bx, C::enc(d[0]), r0 * ES);
 #pragma unroll
       for (int i = 1; i < Q; i += 2)
-        st_pair16<S, CPOL_NT>(plane_ptr(L, i + 1, ES) + r0 * ES, bx, d[i], plane_ptr(L, i, ES) + r0 * ES, bx, d[i + 1]);
+        st_pair16<S, EP>(plane_ptr(L, i + 1, ES) + r0 * ES, bx, d[i], plane_ptr(L, i, ES) + r0 * ES, bx, d[i + 1]);
     } else {
-      Raw<T>::template st<CPOL_NT>(plane_rsrc(L, 0, ES), bx, C::enc(d[0]), r0 * ES);
+      Raw<T>::template st<pol(CP::nt_store(0))>(plane_rsrc(L, 0, ES), bx, C::enc(d[0]), r0 * ES);
       static_for<1, Q, 2>([&](auto I) {
         constexpr int i = decltype(I)::value;
         static_assert(CP::nt_store(i) == CP::nt_store(i + 1), "pair members share a policy");
@@ -561,7 +567,7 @@ k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
   } else if (P == 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i)
-      Raw<T>::template st<CPOL_NT>(plane_rsrc(L, M::OPP[i], ES), bx, C::enc(d[i]), r0 * ES);
+      Raw<T>::template st<EP>(plane_rsrc(L, M::OPP[i], ES), bx, C::enc(d[i]), r0 * ES);
   } else {
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
@@ -581,13 +587,13 @@ k_step_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
 // floor of the step of the same schedule.  (Their set-up code repeats that of
 // the step kernels on purpose: routing both through one shared device
 // function changed the step kernels' register allocation, with SGPR spills.)
-template <class M, int S, int P, bool WIDE, int BLOCK>
+template <class M, int S, int P, bool WIDE, int BLOCK, bool RES>
 __global__ void __launch_bounds__(BLOCK)
 k_propagate(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
             uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
   using Off = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   using T = typename Codec<S>::T;
-  using CP = CachePolicy<M, S, P>;
+  using CP = CachePolicy<M, S, P, RES>;
   constexpr int Q = M::Q;
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, remap);
   uint32_t l = 0;
@@ -618,12 +624,13 @@ k_propagate(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, 
   });
 }
 
-template <class M, int S, int P, int BLOCK>
+template <class M, int S, int P, int BLOCK, bool RES>
 __global__ void __launch_bounds__(BLOCK)
 k_propagate_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ blk, uint32_t nlat,
                  uint32_t remap, const uint64_t* __restrict__ d_t, uint32_t t_off) {
   using T = typename Codec<S>::T;
-  using CP = CachePolicy<M, S, 1>;
+  using CP = CachePolicy<M, S, P, RES>;
+  constexpr int EP = pol(CP::nt_load(0));  // the even step's one policy for every plane
   constexpr int Q = M::Q;
   constexpr uint32_t ES = sizeof(T);
   const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, remap);
@@ -644,9 +651,9 @@ k_propagate_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ 
   T h[Q];
   if (P == 0) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) h[i] = Raw<T>::template ld<CPOL_NT>(plane_rsrc(L, i, ES), bx, r0 * ES);
+    for (int i = 0; i < Q; ++i) h[i] = Raw<T>::template ld<EP>(plane_rsrc(L, i, ES), bx, r0 * ES);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) Raw<T>::template st<CPOL_NT>(plane_rsrc(L, M::OPP[i], ES), bx, h[i], r0 * ES);
+    for (int i = 0; i < Q; ++i) Raw<T>::template st<EP>(plane_rsrc(L, M::OPP[i], ES), bx, h[i], r0 * ES);
     return;
   }
   const uint32_t ym = (y == 0) ? L.wy : 0u - L.nx;

@@ -35,12 +35,14 @@ class LbParams(ctypes.Structure):
 
 class LbSchedule(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("order", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
-                ("xcd_remap", ctypes.c_int32 * 2), ("tiling", ctypes.c_int32 * 2)]
+                ("xcd_remap", ctypes.c_int32 * 2), ("tiling", ctypes.c_int32 * 2),
+                ("resident", ctypes.c_int32), ("group_mb", ctypes.c_int32)]
 
 
 def _sched_dict(s):
     return {"block": s.block, "order": s.order, "graph_chunk": s.graph_chunk,
-            "xcd_remap": list(s.xcd_remap), "tiling": list(s.tiling)}
+            "xcd_remap": list(s.xcd_remap), "tiling": list(s.tiling),
+            "resident": s.resident, "group_mb": s.group_mb}
 
 
 def _pair(v):
@@ -50,8 +52,9 @@ def _pair(v):
     return (ctypes.c_int32 * 2)(int(v), int(v))
 
 
-def _make_schedule(block, order, xcd_remap, graph_chunk, tiling):
-    return LbSchedule(int(block), int(order), int(graph_chunk), _pair(xcd_remap), _pair(tiling))
+def _make_schedule(block, order, xcd_remap, graph_chunk, tiling, resident=0, group_mb=0):
+    return LbSchedule(int(block), int(order), int(graph_chunk), _pair(xcd_remap), _pair(tiling),
+                      int(resident), int(group_mb))
 
 
 # (name, restype, argtypes) of every entry point in include/lbf.h
@@ -273,10 +276,11 @@ class Lattice(_Gathers):
         _check(lib().lb_get_schedule(self._ctx, ctypes.byref(s)), "lb_get_schedule")
         return _sched_dict(s)
 
-    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0):
+    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0, resident=0, group_mb=0):
         """xcd_remap and tiling: an int for both step parities or an
-        (even, odd) pair."""
-        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling)
+        (even, odd) pair; resident: cache every access (1) or stream (0);
+        group_mb: replica groups of at most this many MiB of state (0: one)."""
+        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling, resident, group_mb)
         _check(lib().lb_set_schedule(self._ctx, ctypes.byref(s)), "lb_set_schedule")
 
     def autotune(self, steps=10):
@@ -379,10 +383,11 @@ class Ensemble:
         _check(lib().lb_get_schedule(self._ctx, ctypes.byref(s)), "lb_get_schedule")
         return _sched_dict(s)
 
-    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0):
+    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0, resident=0, group_mb=0):
         """xcd_remap and tiling: an int for both step parities or an
-        (even, odd) pair."""
-        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling)
+        (even, odd) pair; resident: cache every access (1) or stream (0);
+        group_mb: replica groups of at most this many MiB of state (0: one)."""
+        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling, resident, group_mb)
         _check(lib().lb_set_schedule(self._ctx, ctypes.byref(s)), "lb_set_schedule")
 
     def autotune(self, steps=10):

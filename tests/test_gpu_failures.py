@@ -46,7 +46,8 @@ def test_invalid_schedules_rejected():
     lat = lbf.Lattice(**CFG, init="rest")
     before = lat.schedule()
     for bad in [dict(block=96), dict(order=3), dict(graph_chunk=3), dict(graph_chunk=0), dict(xcd_remap=65), dict(xcd_remap=-1),
-                dict(tiling=(0, 5))]:
+                dict(tiling=(0, 5)), dict(resident=2), dict(resident=-1), dict(group_mb=-1),
+                dict(group_mb=(1 << 20) + 1)]:
         args = dict(block=256, order=0, xcd_remap=0, graph_chunk=16, tiling=0)
         args.update(bad)
         with pytest.raises(lb.LBError) as ei:

@@ -118,7 +118,10 @@ def test_graph_direct_and_schedules_bit_identical():
                   dict(block=64, xcd_remap=0, graph_chunk=6, tiling=1),
                   dict(block=256, xcd_remap=(0, 1), graph_chunk=16, tiling=(1, 0)),
                   dict(block=64, xcd_remap=(2, 4), graph_chunk=16, tiling=(0, 1)),
-                  dict(block=128, xcd_remap=(3, 2), graph_chunk=10, tiling=(1, 1))]:
+                  dict(block=128, xcd_remap=(3, 2), graph_chunk=10, tiling=(1, 1)),
+                  dict(block=256, xcd_remap=0, graph_chunk=16, tiling=(1, 0), resident=1),
+                  dict(block=64, xcd_remap=(2, 4), graph_chunk=4, tiling=(0, 1), resident=1),
+                  dict(block=128, xcd_remap=1, graph_chunk=6, tiling=1, resident=1, group_mb=1)]:
         lat = lbf.Lattice(**cfg, init="thermal")
         lat.set_schedule(**sched)
         lat.step(37)

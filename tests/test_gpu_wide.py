@@ -30,6 +30,9 @@ def test_1024_fp32_wide_planes_sampled_parity():
     with pytest.raises(lb.LBError) as ei:
         lat.set_schedule(block=256, tiling=1)
     assert ei.value.code == lb.LB_EUNSUPPORTED
+    with pytest.raises(lb.LBError) as ei:
+        lat.set_schedule(block=256, tiling=0, resident=1)
+    assert ei.value.code == lb.LB_EUNSUPPORTED
     pts = sample_sites(L, 600, seed=9)
     check_one_step(lat, cfg, pts, 1e-5)      # even step
     lat.step(18)                             # one direct step, one 16-step graph replay, one more: t = 19
