@@ -258,13 +258,14 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
  * odd (remap, tiling) choices sum lowest.  A second stage times that
  * schedule on whole graph replays (at least 2 * `steps` steps, three
  * interleaved rounds) with each cache policy and, for a batch, replica
- * groups of 0, 64, 128, 160, 192 and 224 MiB, and keeps a variant only if
- * it is at least 1% faster than the first stage's choice.  Applies the best
- * schedule and writes a JSON report (one object per first-stage candidate with its
- * mean even and odd step times, plus refined_even_ms / refined_odd_ms for
- * the re-timed ones; then one object per second-stage variant with its
- * resident, group_mb and ms_per_step) into report (NUL-terminated,
- * truncated to report_len).  Allocates a scratch copy of the state. */
+ * groups of 0, 64, 128, 160, 192, 224 and 256 MiB, and keeps a variant
+ * only if it is at least 1% faster than the first stage's choice.  Applies
+ * the best schedule and writes a JSON report (one object per first-stage
+ * candidate with its mean even and odd step times, plus refined_even_ms /
+ * refined_odd_ms for the re-timed ones; then one object per second-stage
+ * variant with its resident, group_mb and ms_per_step) into report
+ * (NUL-terminated, truncated to report_len).  Allocates a scratch copy of
+ * the state. */
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
 
 /* ---- calibration ---- */

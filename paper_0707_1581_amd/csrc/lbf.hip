@@ -995,8 +995,8 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   };
   std::vector<Var> vars;
   {
-    const int gmbs[] = {0, 64, 128, 160, 192, 224};
-    const int ngmb = ctx->lats.size() > 1 ? 6 : 1;
+    const int gmbs[] = {0, 64, 128, 160, 192, 224, 256};
+    const int ngmb = ctx->lats.size() > 1 ? 7 : 1;
     for (int res = 0; res < (ctx->wide ? 1 : 2); ++res)
       for (int gi = 0; gi < ngmb; ++gi) vars.push_back({res, gmbs[gi], 0.0});
   }
