@@ -518,12 +518,32 @@ int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity
 // without XCD remapping; the 16-bit forms run the even step flat and the odd
 // step row-tiled, with XCD groups of 8 consecutive tiles on D3Q19 and no
 // remapping on D2Q9 (groups of 8 made the D2Q9 bf16 step 10% slower).
-// lb_autotune refines it for a given workload.
+// State of 32 MB to 320 MB on one lattice runs resident in the Infinity
+// Cache (4-14% faster from 96^3 to 160^3); a batch whose replicas each fit
+// in 224 MiB runs resident groups of 224 MiB once it holds 32 MB or more
+// (the 96-replica fp32 ensemble: 11% faster).  Below 32 MB the streaming
+// policy measured as fast or faster.  lb_autotune refines it for a given
+// workload.
 int default_schedule(lb_ctx* c) {
   if (c->storage == LB_F32) c->sched = lb_schedule{256, 0, 16, {0, 0}, {1, 0}, 0, 0};
   else if (c->lattice == LB_D2Q9) c->sched = lb_schedule{256, 0, 16, {0, 0}, {0, 1}, 0, 0};
   else c->sched = lb_schedule{256, 0, 16, {8, 8}, {0, 1}, 0, 0};
   if (c->wide) c->sched.tiling[0] = c->sched.tiling[1] = 0;
+  if (!c->wide) {
+    uint64_t total = 0, largest = 0;
+    for (const lb_params& p : c->reps) {
+      const uint64_t b = (uint64_t)q_of(p.lattice) * sites_of(p) * elem_size(p.storage);
+      total += b;
+      largest = std::max(largest, b);
+    }
+    constexpr uint64_t MB = 1000000, MIB = 1ull << 20;
+    if (c->reps.size() == 1) {
+      if (total >= 32 * MB && total <= 320 * MB) c->sched.resident = 1;
+    } else if (total >= 32 * MB && largest <= 224 * MIB) {
+      c->sched.resident = 1;
+      c->sched.group_mb = 224;
+    }
+  }
   return upload_schedule(c);
 }
 
