@@ -291,3 +291,32 @@ def test_replica_groups_and_resident_policy(storage):
             for r in range(len(reps)):
                 assert torch.equal(moved[r], prop_ref[r]), (sched, r)
         ens.close()
+
+
+def test_default_schedule_cache_policy():
+    """The default schedule runs state that fits in the Infinity Cache
+    resident: a single lattice of 32-320 MB, and a batch of 32 MB or more
+    whose replicas each fit in 224 MiB (then in 224 MiB groups); tiny state
+    and batches with a larger replica stream."""
+    base = dict(rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=0.0, gamma_even=0.0, seed=9)
+    cases = [(dict(nx=48, ny=48, nz=48), "f32", (0, 0)),       # 8.4 MB
+             (dict(nx=128, ny=128, nz=128), "f32", (1, 0)),    # 159 MB
+             (dict(nx=160, ny=160, nz=160), "f16", (1, 0)),    # 156 MB
+             (dict(nx=192, ny=192, nz=192), "f32", (0, 0))]    # 538 MB
+    for dims, st, want in cases:
+        lat = lbf.Lattice(**dims, **base, storage=st, init="rest")
+        s = lat.schedule()
+        assert (s["resident"], s["group_mb"]) == want, (dims, st, s)
+        lat.close()
+    four = [dict(base, nx=96, ny=96, nz=96, seed=s) for s in range(4)]          # 4 x 67 MB
+    ens = lbf.Ensemble(four, init="rest")
+    assert (ens.schedule()["resident"], ens.schedule()["group_mb"]) == (1, 224)
+    ens.close()
+    mixed = [dict(base, nx=160, ny=160, nz=160)] + [dict(base, nx=32, ny=32, nz=32, seed=s) for s in range(3)]
+    ens = lbf.Ensemble(mixed, init="rest")                                       # one 311 MB replica
+    assert (ens.schedule()["resident"], ens.schedule()["group_mb"]) == (0, 0)
+    ens.close()
+    small = [dict(base, nx=16, ny=16, nz=16, seed=s) for s in range(8)]          # 2.5 MB in all
+    ens = lbf.Ensemble(small, init="rest")
+    assert (ens.schedule()["resident"], ens.schedule()["group_mb"]) == (0, 0)
+    ens.close()
