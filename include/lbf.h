@@ -144,8 +144,10 @@ int lb_step(lb_ctx* ctx, int64_t nsteps);
  * as with lb_step, keeping the parity-resolved layout consistent (later
  * collisions draw the noise of the advanced counter).  On a batch every
  * replica moves.  Each step is one launch over the tiles of the current
- * schedule, with the memory accesses and cache policy of the step kernel
- * it replaces, so its duration is the data-movement floor of that step. */
+ * schedule (one per replica group), with the memory accesses and cache
+ * policy of the step kernel it replaces, so its duration is the
+ * data-movement floor of that step.  Steps are launched one by one, never
+ * from a graph replay. */
 int lb_propagate(lb_ctx* ctx, int64_t nsteps);
 
 /* Parity-resolved gathers into caller-owned fp32 device buffers, each laid
