@@ -192,7 +192,7 @@ const char* lb_last_error(void);
 int lb_params_from_physical(double b, double h, double rho, double eta, double zeta, double kBT,
                             lb_params* p);
 
-/* ---- ensembles: many independent lattices in one launch per step ---- */
+/* ---- ensembles: many independent lattices, one launch per step (per replica group) ---- */
 
 /* Bytes of the pool for nrep replicas: each replica's state rounded up to
  * 256 bytes, in order; 0 if any replica is invalid. */

@@ -58,16 +58,16 @@ def check_one_step(lat, cfg, pts, tol):
     assert worst < tol, worst
 
 
-@pytest.mark.parametrize("remap,rows", [(None, None), (0, 0), (1, 1)])
-def test_512_fp32_sampled_parity(remap, rows):
+@pytest.mark.parametrize("remap,rows,resident", [(None, None, 0), (0, 0, 0), (1, 1, 0), (0, (1, 0), 1)])
+def test_512_fp32_sampled_parity(remap, rows, resident):
     """None: the library's default schedule (the one the benchmark starts its
-    tuning from)."""
+    tuning from); resident: the kernels of the resident cache policy."""
     cfg = dict(workloads.LARGE)
-    say(f"512^3 fp32, xcd_remap={remap}, tiling={rows}")
+    say(f"512^3 fp32, xcd_remap={remap}, tiling={rows}, resident={resident}")
     lat = lbf.Lattice(**cfg, storage="f32", init="thermal")
     if remap is not None:
-        lat.set_schedule(block=256, order=0, xcd_remap=remap, graph_chunk=16, tiling=rows)
-    pts = sample_sites(512, 1500, seed=remap)
+        lat.set_schedule(block=256, order=0, xcd_remap=remap, graph_chunk=16, tiling=rows, resident=resident)
+    pts = sample_sites(512, 1500, seed=100 if remap is None else remap + 10 * resident)
     check_one_step(lat, cfg, pts, 1e-5)      # even step (t = 0)
     lat.step(17)                             # one direct step and one 16-step graph replay: t = 18
     lat.step(1)                              # t = 19
