@@ -133,7 +133,9 @@ int lb_init(const lb_params* p, void* d_state, void* hip_stream, int32_t init_ki
             const float* d_fields, int64_t t0, lb_ctx** out);
 
 /* Enqueue nsteps >= 0 steps (collide with noise keyed on the current t,
- * then push).  Full chunks of steps are replayed from a HIP graph. */
+ * then push).  Full chunks of steps are replayed from a HIP graph (launched
+ * one by one instead when a replay would exceed 2^16 kernel launches:
+ * graph_chunk times the number of replica groups). */
 int lb_step(lb_ctx* ctx, int64_t nsteps);
 
 /* Enqueue nsteps >= 0 propagation-only steps: the streaming half of

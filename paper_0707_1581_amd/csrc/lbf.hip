@@ -455,7 +455,10 @@ int advance(lb_ctx* c, int64_t n) {
     if (rc) return rc;
     --n;
   }
-  if (n >= K) {
+  // a replay holds K launches per replica group; past 2^16 kernel nodes the
+  // steps are launched directly instead (same work, more host launches)
+  const bool graphable = (uint64_t)K * c->groups.size() <= (1u << 16);
+  if (n >= K && graphable) {
     if (!c->graph_exec) {
       int rc = build_graph(c);
       if (rc) return rc;
@@ -466,7 +469,12 @@ int advance(lb_ctx* c, int64_t n) {
       n -= K;
     }
   }
-  if (n > 0) return direct_steps(c, n);
+  while (n > 0) {  // the device counter advances every K steps, as in a replay
+    const int64_t m = std::min<int64_t>(n, K);
+    int rc = direct_steps(c, m);
+    if (rc) return rc;
+    n -= m;
+  }
   return LB_OK;
 }
 

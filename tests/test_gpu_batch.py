@@ -320,3 +320,28 @@ def test_default_schedule_cache_policy():
     ens = lbf.Ensemble(small, init="rest")
     assert (ens.schedule()["resident"], ens.schedule()["group_mb"]) == (0, 0)
     ens.close()
+
+
+def test_many_groups_step_without_a_graph():
+    """65 replicas of 1.002 MiB each with 1 MiB groups are 65 groups; with
+    graph_chunk 1024 a replay would hold 66,560 kernel nodes, past the
+    library's limit of 65,536, so the steps are launched directly.  The
+    states after 1030 steps equal those of a graphed schedule and, for a
+    few replicas, of their standalone runs."""
+    reps = [dict(nx=24, ny=24, nz=24, rho0=1.0, kT=float(kT), gamma_bulk=0.5, gamma_shear=0.6, gamma_odd=0.0,
+                 gamma_even=0.0, seed=900 + r) for r, kT in enumerate(np.linspace(1e-5, 1e-3, 65))]
+    steps = 1030
+    states = []
+    for sched in [dict(block=256, order=0, xcd_remap=0, graph_chunk=1024, tiling=0, resident=1, group_mb=1),
+                  dict(block=256, order=0, xcd_remap=0, graph_chunk=16, tiling=0, resident=1, group_mb=8)]:
+        ens = lbf.Ensemble(reps, init="thermal")
+        ens.set_schedule(**sched)
+        ens.step(steps)
+        assert ens.t == steps
+        states.append([ens.replica_state(r).clone() for r in range(len(reps))])
+        ens.close()
+    for r in range(len(reps)):
+        assert torch.equal(states[0][r], states[1][r]), r
+    want = standalone_states([reps[r] for r in (0, 32, 64)], "f32", steps)
+    for w, r in zip(want, (0, 32, 64)):
+        assert torch.equal(states[0][r], w), r
