@@ -6,9 +6,9 @@ pattern, one buffer of 10.2 GB), rho0 = 1, kT = 1e-4, gamma_shear = 0.8,
 gamma_bulk = 0.5, kinetic rates 0, thermal (random seeded rest) start with
 Philox seed 1234.  One step = the whole fused collide-and-stream update of
 every site.  The same box is also timed with fp16 and bf16 storage, a 768^3
-box in all three storage forms, the 96-replica ensemble in one launch per
-step, and the D2Q9 lattice (Table I) on a 16384^2 box (2^28 sites) with fp32
-and bf16 storage.
+box in all three storage forms, the 96-replica ensemble (one launch per
+step and replica group, autotuned), and the D2Q9 lattice (Table I) on a
+16384^2 box (2^28 sites) with fp32 and bf16 storage.
 
 Prints one JSON line.  `value` is MLUPS (million lattice-site updates per
 second) of the fp32 run with the state resident in HBM; `roofline` compares

@@ -323,7 +323,7 @@ class ReplicaView(_Gathers):
 
 class Ensemble:
     """Independent replicas (own box, rates, kT, seed; one storage type and
-    one lattice) advanced together, one kernel launch per step for all of
+    one lattice) advanced together, one kernel launch per step (per replica group) for all of
     them."""
 
     def __init__(self, replicas, storage="f32", init="thermal", t0=0, device="cuda", stream=None,
