@@ -179,6 +179,72 @@ def extrapolate_q0(qs2, vals):
     return coef[0]
 
 
+# ---------------------------------------------------------------- stationary law of the linear update
+def stationary_mode_variances(dims, gammas, noisy, c, a, e, w, structure_factor=False, batch=2048,
+                              doublings=16):
+    """Equal-time per-site mode variances of the linearised fluctuating
+    update on a periodic box, in units of mu rho w_k.
+
+    For small noise the deviation from rest evolves, per wave vector q, as
+    x(t + 1) = S(q) (C x(t) + xi(t)) with C = Minv diag(gamma) M the
+    collision, S(q) = diag(exp(-i q.c_i)) the push and xi the collision
+    noise: sqrt(w_k (1 - gamma_k^2)) r_k on the modes flagged in `noisy`
+    (mu rho = 1), none elsewhere.  The stationary covariance solves the
+    discrete Lyapunov equation X = A X A^H + S B S^H with A = S C and
+    B = Minv diag(noise variances) Minv^T; it is summed here as
+    X = sum_n A^n (S B S^H) A^nH by repeated squaring.  The per-site
+    covariance is the average of X(q) over the box's wave vectors, and
+    the mode variances are the diagonal of M (that average) M^T, divided by
+    w_k.  Conserved modes carry no noise, so at q = 0 they do not
+    fluctuate: the result for k <= d is the variance about the lattice
+    mean, as measured.
+
+    With every non-conserved mode noisy (the detailed-balance collision,
+    Sec. IV) the result is 1 for the non-conserved modes and 1 - 1/N for
+    the conserved ones (the q = 0 part is missing).  With noise on the
+    stress modes only (the earlier model the paper contrasts) it is not.
+
+    With structure_factor=True also returns {|q|^2: mean S(q) / (mu rho)}
+    over the nonzero wave vectors (the density-density correlation of mode
+    0, Eq. mpeos's mu rho for the detailed-balance collision)."""
+    M = np.asarray(e, dtype=float)
+    q = M.shape[0]
+    wv = np.asarray(w, dtype=float)
+    g = np.asarray(gammas, dtype=float)
+    Minv = (np.asarray(a)[:, None] * M.T) / wv[None, :]
+    C = Minv @ np.diag(g) @ M
+    nv = np.where(np.asarray(noisy, bool), wv * (1.0 - g * g), 0.0)
+    B = Minv @ np.diag(nv) @ Minv.T
+    cf = np.asarray(c, dtype=float)
+    dims = tuple(int(v) for v in dims)
+    grids = np.meshgrid(*[np.arange(n) * (2 * np.pi / n) for n in dims], indexing="ij")
+    qs = np.stack([gr.ravel() for gr in grids], axis=1)  # (N, 3)
+    N = qs.shape[0]
+    acc = np.zeros((q, q))
+    sq = {}
+    for s0 in range(0, N, batch):
+        qv = qs[s0:s0 + batch]
+        ph = np.exp(-1j * (qv @ cf.T))  # (b, q)
+        A = ph[:, :, None] * C[None, :, :]
+        X = ph[:, :, None] * B[None, :, :] * ph.conj()[:, None, :]
+        Ap = A
+        for _ in range(doublings):  # 2^doublings terms: far past the slowest decay of a box <= 64
+            X = X + Ap @ X @ np.conj(np.swapaxes(Ap, 1, 2))
+            Ap = Ap @ Ap
+        acc += X.real.sum(axis=0)
+        if structure_factor:
+            s00 = np.einsum("i,bij,j->b", M[0], X, M[0]).real
+            q2 = np.round((qv * qv).sum(axis=1), 12)
+            for k2, v in zip(q2, s00):
+                if k2 > 0:
+                    sq.setdefault(k2, []).append(v)
+    acc /= N
+    mv = np.diag(M @ acc @ M.T) / wv
+    if structure_factor:
+        return mv, {k2: float(np.mean(v)) for k2, v in sorted(sq.items())}
+    return mv
+
+
 # ---------------------------------------------------------------- statistics
 def neq_modes(modes, rho0):
     """Non-equilibrium part of the unscaled modes, (19, ...) array of m_k of

@@ -11,7 +11,9 @@
   give the kinematic viscosity c_s^2 (1 + g_s) / (2 (1 - g_s)) of Eq.
   shearviscosity (after removing the O(q^2) lattice correction).
 * The earlier model with noise on the stress modes only (Sec. IV) leaves the
-  kinetic modes under-thermalised: their variances fall short of mu rho w_k.
+  kinetic modes under-thermalised, and through streaming every other mode
+  too: all 19 variances follow the linear theory of that model, well short
+  of mu rho w_k.
 """
 import numpy as np
 import pytest
@@ -161,27 +163,38 @@ def test_viscosity_q0_limit_gamma09():
     assert nu0 == pytest.approx(th.nu_closed_form(gs), rel=0.01)
 
 
-def test_stress_only_noise_underthermalises_kinetic_modes():
+def test_stress_only_noise_matches_its_linear_theory():
     """With noise on the stress modes only (the earlier model the paper
-    contrasts), kinetic-mode variances fall well below mu rho w_k while the
-    full detailed-balance collision keeps them at mu rho w_k."""
+    contrasts), every mode's stationary variance is that of the linearised
+    update with noise on modes 4..9 alone (the discrete Lyapunov equation
+    per wave vector, tests/lbtheory.py): the kinetic modes reach only 26-38%
+    of mu rho w_k and, through streaming, the stress and conserved modes
+    fall short too (31-51%).  The full detailed-balance collision keeps
+    every mode at mu rho w_k.  Both checked to 1% on 32^3."""
     base = dict(nx=32, ny=32, nz=32, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.5,
                 gamma_odd=0.0, gamma_even=0.0, seed=77)
     mu = 3e-4
+    c, a, e, w = oracle.tables()
+    g = th.mode_gammas(0.5, 0.5, 0.0, 0.0)
+    noisy = np.zeros(19, bool)
+    noisy[4:10] = True
+    theory = th.stationary_mode_variances((32, 32, 32), g, noisy, c, a, e, w)
     res = {}
     for mode in ("all", "stress_only"):
         lat = lbf.Lattice(**base, thermal_modes=mode, init="thermal")
         lat.step(200)
         acc = np.zeros(19)
-        for _ in range(40):
+        nsnap = 80
+        for _ in range(nsnap):
             lat.step(5)
             v, rbar = neq_variances(lat.modes(), 1.0)
             acc += v / (mu * rbar * W)
-        res[mode] = acc / 40
+        res[mode] = acc / nsnap
         lat.close()
-    say(f"kinetic-mode variance ratios: all {res['all'][10:].round(3)}, stress-only {res['stress_only'][10:].round(3)}")
-    assert np.all(np.abs(res["all"] - 1) < 0.02)
-    assert np.all(res["stress_only"][10:] < 0.9)
+    say(f"stress-only variance ratios: measured {res['stress_only'].round(4)}, theory {theory.round(4)}")
+    assert np.all(np.abs(res["all"] - 1) < 0.01)
+    np.testing.assert_allclose(res["stress_only"], theory, rtol=0.01)
+    assert np.all(res["stress_only"][10:] < 0.4) and np.all(res["stress_only"][4:10] < 0.55)
 
 
 @pytest.mark.parametrize("gb,gs", [(0.3, 0.5), (0.8, 0.0)])
