@@ -78,6 +78,11 @@ enum lb_status {
   LB_EUNSUPPORTED = -4  /* valid request the library does not provide   */
 };
 
+/* Storage of the state.  LB_BF16 is meant for fluctuating runs (kT > 0):
+ * without noise its 8-bit mantissa biases slowly varying fields (a
+ * noiseless shear wave decays about 2% too slowly), so deterministic runs
+ * should store fp16 or fp32; lb_init accepts it and leaves a warning in
+ * lb_last_error(). */
 enum lb_storage { LB_F32 = 0, LB_F16 = 1, LB_BF16 = 2 };
 
 enum lb_lattice {
@@ -128,7 +133,12 @@ size_t lb_state_bytes(const lb_params* p);
 /* Validate p and create a context that updates d_state on hip_stream.
  * Enqueues the initial state (init_kind) as the state at step count t0
  * (t0 >= 0); d_fields is required for LB_INIT_FIELDS and ignored otherwise.
- * The context stores p by value. */
+ * The context stores p by value.  Its default schedule (lb_get_schedule)
+ * depends on the state: an fp32 D3Q19 lattice of more than 320 MB with
+ * planes below 4 GiB takes the fused two-step schedule when the device has
+ * room for its second state buffer, which lb_init then allocates (release
+ * it with lb_set_schedule and fused = 0).  With LB_BF16 storage and kT = 0
+ * it succeeds and leaves a warning in lb_last_error(). */
 int lb_init(const lb_params* p, void* d_state, void* hip_stream, int32_t init_kind,
             const float* d_fields, int64_t t0, lb_ctx** out);
 
@@ -176,6 +186,8 @@ int64_t lb_step_count(const lb_ctx* ctx);
 void lb_destroy(lb_ctx* ctx);
 
 const char* lb_strerror(int code);
+/* Message of the last failure on the calling thread (or the warning of a
+ * later lb_init that succeeded with one); never NULL. */
 const char* lb_last_error(void);
 
 /* Lattice parameters from physical ones (Sec. VI, choice of parameters).
@@ -247,6 +259,21 @@ typedef struct {
                         /* group, and a graph replay runs all graph_chunk      */
                         /* steps of one group before the next.  Replicas are   */
                         /* independent, so results do not depend on it.        */
+  int32_t fused;        /* 0: one in-place AA launch per step.  1: two steps   */
+                        /* per launch: from even t, each launch reads the      */
+                        /* state once and writes the state two steps later     */
+                        /* into a second buffer that the library allocates     */
+                        /* (the size of the state) and releases when the       */
+                        /* schedule goes back to 0 or the context is           */
+                        /* destroyed.  Pairs of launches return the state to   */
+                        /* the caller's buffer, so between calls it is always  */
+                        /* there; steps that do not fill a pair of launches    */
+                        /* run as AA steps.  Results are bit-identical to      */
+                        /* fused = 0.  Single D3Q19 lattices with planes below */
+                        /* 4 GiB only (else LB_EUNSUPPORTED, as when the       */
+                        /* second buffer cannot be allocated); the tiling,     */
+                        /* remap and cache-policy fields then apply to those   */
+                        /* AA steps only.                                      */
 } lb_schedule;
 
 int lb_get_schedule(const lb_ctx* ctx, lb_schedule* out);
@@ -263,13 +290,16 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
  * schedule on whole graph replays (at least 2 * `steps` steps, three
  * interleaved rounds) with each cache policy and, for a batch, replica
  * groups of 0, 64, 128, 160, 192, 224 and 256 MiB, and keeps a variant
- * only if it is at least 1% faster than the first stage's choice.  Applies
- * the best schedule and writes a JSON report (one object per first-stage
- * candidate with its mean even and odd step times, plus refined_even_ms /
- * refined_odd_ms for the re-timed ones; then one object per second-stage
- * variant with its resident, group_mb and ms_per_step) into report
- * (NUL-terminated, truncated to report_len).  Allocates a scratch copy of
- * the state. */
+ * only if it is at least 1% faster than the first stage's choice; a single
+ * D3Q19 lattice also tries the fused two-step schedule there (when the
+ * device has room for its second buffer).  Applies the best schedule and
+ * writes a JSON report (one object per first-stage candidate with its mean
+ * even and odd step times, plus refined_even_ms / refined_odd_ms for the
+ * re-timed ones; then one object per second-stage variant with its
+ * resident, group_mb, fused and ms_per_step) into report (NUL-terminated,
+ * truncated to report_len).  Allocates a scratch copy of the state for as
+ * long as it runs; returns LB_EUNSUPPORTED, having changed nothing, when the
+ * device's free memory cannot hold that copy. */
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
 
 /* ---- calibration ---- */

@@ -17,6 +17,10 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # no packed-fp32 VALU instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds are fused only within one source expression, so every
+    # kernel that inlines the collision computes the same bits (the fused
+    # two-step pass equals two single steps bit for bit)
+    "-ffp-contract=on",
     "-Wall", "-Wno-unused-function",
 ]
 

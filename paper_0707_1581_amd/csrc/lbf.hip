@@ -197,6 +197,17 @@ void* rows_ptr(int lattice, int storage, int parity, bool res, int block, bool p
                             : rows_ptr_m<D3Q19, false>(storage, parity, res, block);
 }
 
+// Fused two-step passes (D3Q19, planes below 4 GiB): step kernels and their
+// propagation-only twins.
+void* step2_ptr(int storage, bool prop) {
+  switch (storage) {
+    case LB_F32: return prop ? (void*)&k_step2<ST_F32, true> : (void*)&k_step2<ST_F32, false>;
+    case LB_F16: return prop ? (void*)&k_step2<ST_F16, true> : (void*)&k_step2<ST_F16, false>;
+    case LB_BF16: return prop ? (void*)&k_step2<ST_BF16, true> : (void*)&k_step2<ST_BF16, false>;
+  }
+  return nullptr;
+}
+
 // Initial states (rest, thermal, fields), gathers (populations, moments,
 // modes) and the health check; init and gather kinds are template
 // parameters of their kernels.
@@ -265,7 +276,7 @@ struct lb_ctx {
   double* h_result = nullptr;   // pinned
   std::vector<LatDesc> lats;
 
-  lb_schedule sched{256, 0, 16, {0, 0}, {1, 0}, 0, 0};
+  lb_schedule sched{256, 0, 16, {0, 0}, {1, 0}, 0, 0, 0};
   // Lattices in tile order are split into groups of consecutive lattices
   // (one group unless sched.group_mb is set); every step is one launch per
   // group, and a graph chunk runs all its steps on one group before the next.
@@ -291,6 +302,21 @@ struct lb_ctx {
     uint64_t* d_t;
     uint64_t n;
   } adv_args;
+
+  // fused schedule: the second state buffer (library-owned), the descriptors
+  // of both buffers (d_f2[0] the state, d_f2[1] the second buffer) and the
+  // tile grid of k_step2
+  char* d_state_b = nullptr;
+  LatDesc* d_f2 = nullptr;
+  uint32_t f2_ntx = 0, f2_nty = 0, f2_ntz = 0;
+  static constexpr uint32_t F2_ZLEN = 32;  // planes per tile column (measured: 32 beats 64 and 128 at 512^3)
+  struct F2Args {
+    const LatDesc* src;
+    uint64_t dst;
+    const uint64_t* d_t;
+    uint32_t t_off, ntx, nty, zlen;
+  };
+  std::vector<F2Args> graph_f2_args;
 
   lb_ctx* root() { return parent ? parent : this; }
 };
@@ -351,8 +377,45 @@ int upload_schedule(lb_ctx* c) {
   HIP_TRY(hipMemcpy(c->d_tile_lats, tl.data(), sizeof(LatDesc) * nlat, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_blk, blk.data(), sizeof(uint32_t) * (nlat + 1), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(c->d_blk_rows, blk_rows.data(), sizeof(uint32_t) * (nlat + 1), hipMemcpyHostToDevice));
+  if (c->sched.fused) {
+    // descriptors of the state buffer and of the second buffer (same geometry)
+    LatDesc f2[2] = {c->lats[0], c->lats[0]};
+    f2[1].base = (uint64_t)(uintptr_t)c->d_state_b;
+    HIP_TRY(hipMemcpy(c->d_f2, f2, sizeof(f2), hipMemcpyHostToDevice));
+    c->f2_ntx = (f2[0].nx + 63u) / 64u;
+    c->f2_nty = (f2[0].ny + (uint32_t)F2_TY - 1u) / (uint32_t)F2_TY;
+    c->f2_ntz = (f2[0].nz + lb_ctx::F2_ZLEN - 1u) / lb_ctx::F2_ZLEN;
+  }
   drop_graph(c);
   return LB_OK;
+}
+
+// The fused schedule's second buffer: allocated once, the size of the state,
+// if the device has room for it beside a margin of 1 GiB.
+bool fused_eligible(const lb_ctx* c) { return c->lattice == LB_D3Q19 && c->reps.size() == 1 && !c->wide; }
+
+int ensure_state_b(lb_ctx* c) {
+  if (c->d_state_b) return LB_OK;
+  const size_t bytes = (size_t)q_of(c->lattice) * sites_of(c->reps[0]) * elem_size(c->storage);
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  if (free_b < bytes + (1ull << 30))
+    return fail(LB_EUNSUPPORTED, "not enough free device memory for the fused schedule's second state buffer");
+  const hipError_t e = hipMalloc(&c->d_state_b, bytes);
+  if (e != hipSuccess) {
+    c->d_state_b = nullptr;
+    (void)hipGetLastError();
+    return fail(LB_EUNSUPPORTED, std::string("second state buffer of the fused schedule: ") + hipGetErrorString(e));
+  }
+  return LB_OK;
+}
+
+void release_state_b(lb_ctx* c) {
+  if (!c->d_state_b) return;
+  drop_graph(c);
+  (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->d_state_b);
+  c->d_state_b = nullptr;
 }
 
 // Kernel, grid, workgroup size, lattices and tile prefix of the launch of
@@ -388,6 +451,22 @@ int launch_step(lb_ctx* c, uint32_t t_off, int parity, bool prop = false) {
   return LB_OK;
 }
 
+// One fused pass (two steps from even t + t_off): state buffer -> second
+// buffer (to_b) or back.
+lb_ctx::F2Args pass_args(const lb_ctx* c, uint32_t t_off, bool to_b) {
+  return {to_b ? c->d_f2 : c->d_f2 + 1,
+          to_b ? (uint64_t)(uintptr_t)c->d_state_b : c->lats[0].base,
+          c->d_t, t_off, c->f2_ntx, c->f2_nty, lb_ctx::F2_ZLEN};
+}
+
+int launch_pass(lb_ctx* c, uint32_t t_off, bool to_b, bool prop = false) {
+  lb_ctx::F2Args a = pass_args(c, t_off, to_b);
+  void* args[] = {&a.src, &a.dst, &a.d_t, &a.t_off, &a.ntx, &a.nty, &a.zlen};
+  HIP_TRY(hipLaunchKernel(step2_ptr(c->storage, prop), dim3(c->f2_ntx * c->f2_nty * c->f2_ntz), dim3(F2_THREADS),
+                          args, 0, c->stream));
+  return LB_OK;
+}
+
 int launch_advance(lb_ctx* c, uint64_t n) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, c->stream, c->d_t, n);
   HIP_TRY(hipGetLastError());
@@ -396,48 +475,71 @@ int launch_advance(lb_ctx* c, uint64_t n) {
 
 // A chain of graph_chunk steps of each group in turn (all steps of one group
 // before the next, so a group whose state fits in the Infinity Cache stays
-// there), then the counter advance.
+// there), then the counter advance.  Under the fused schedule (one lattice)
+// the chain is fused passes, out to the second buffer and back, for every
+// four steps, and AA steps for the rest of the chunk.
 int build_graph(lb_ctx* c) {
   drop_graph(c);
   const int K = c->sched.graph_chunk;
+  const int units = c->sched.fused ? K / 4 : 0;  // pairs of fused passes
   HIP_TRY(hipGraphCreate(&c->graph, 0));
-  c->graph_args.assign(K * c->groups.size(), {});
+  c->graph_args.assign((K - 4 * units) * c->groups.size(), {});
+  c->graph_f2_args.assign(2 * units, {});
   hipGraphNode_t prev = nullptr;
-  for (size_t n = 0; n < c->graph_args.size(); ++n) {
-    const size_t g = n / K;
-    const int s = (int)(n % K);
-    const StepLaunch sl = step_launch(c, s & 1, g);
-    if (!sl.fn) return fail(LB_EINVAL, "no step kernel for this schedule");
-    c->graph_args[n] = {sl.lats, sl.blk, sl.nlat, (uint32_t)c->sched.xcd_remap[s & 1], c->d_t, (uint32_t)s};
-    lb_ctx::StepArgs& a = c->graph_args[n];
-    void* args[] = {&a.lats, &a.blk, &a.nlat, &a.remap, &a.d_t, &a.t_off};
+  auto add_node = [&](void* fn, uint32_t grid, int block, void** args) -> int {
     hipKernelNodeParams kp{};
-    kp.func = sl.fn;
-    kp.gridDim = dim3(sl.grid);
-    kp.blockDim = dim3(sl.block);
+    kp.func = fn;
+    kp.gridDim = dim3(grid);
+    kp.blockDim = dim3(block);
     kp.sharedMemBytes = 0;
     kp.kernelParams = args;
     kp.extra = nullptr;
     hipGraphNode_t node;
     HIP_TRY(hipGraphAddKernelNode(&node, c->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
     prev = node;
+    return LB_OK;
+  };
+  for (int p = 0; p < 2 * units; ++p) {
+    c->graph_f2_args[p] = pass_args(c, (uint32_t)(2 * p), (p & 1) == 0);
+    lb_ctx::F2Args& a = c->graph_f2_args[p];
+    void* args[] = {&a.src, &a.dst, &a.d_t, &a.t_off, &a.ntx, &a.nty, &a.zlen};
+    int rc = add_node(step2_ptr(c->storage, false), c->f2_ntx * c->f2_nty * c->f2_ntz, F2_THREADS, args);
+    if (rc) return rc;
+  }
+  const int K1 = K - 4 * units;  // AA steps per group, from step 4 * units of the chunk
+  for (size_t n = 0; n < c->graph_args.size(); ++n) {
+    const size_t g = n / K1;
+    const int s = 4 * units + (int)(n % K1);
+    const StepLaunch sl = step_launch(c, s & 1, g);
+    if (!sl.fn) return fail(LB_EINVAL, "no step kernel for this schedule");
+    c->graph_args[n] = {sl.lats, sl.blk, sl.nlat, (uint32_t)c->sched.xcd_remap[s & 1], c->d_t, (uint32_t)s};
+    lb_ctx::StepArgs& a = c->graph_args[n];
+    void* args[] = {&a.lats, &a.blk, &a.nlat, &a.remap, &a.d_t, &a.t_off};
+    int rc = add_node(sl.fn, sl.grid, sl.block, args);
+    if (rc) return rc;
   }
   c->adv_args = {c->d_t, (uint64_t)K};
   void* aargs[] = {&c->adv_args.d_t, &c->adv_args.n};
-  hipKernelNodeParams kp{};
-  kp.func = (void*)&k_advance;
-  kp.gridDim = dim3(1);
-  kp.blockDim = dim3(64);
-  kp.kernelParams = aargs;
-  hipGraphNode_t node;
-  HIP_TRY(hipGraphAddKernelNode(&node, c->graph, &prev, 1, &kp));
+  int rc = add_node((void*)&k_advance, 1, 64, aargs);
+  if (rc) return rc;
   HIP_TRY(hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
   return LB_OK;
 }
 
-int direct_steps(lb_ctx* c, int64_t m) {
-  for (int64_t s = 0; s < m; ++s) {
-    int rc = launch_step(c, (uint32_t)s, (int)((c->t + s) & 1));
+// m steps launched one by one (prop: the propagation-only kernels), then the
+// counter advance.  Under the fused schedule, from even t, every four steps
+// run as two fused passes (out to the second buffer and back).
+int direct_steps(lb_ctx* c, int64_t m, bool prop = false) {
+  int64_t s = 0;
+  if (c->sched.fused && !(c->t & 1)) {
+    for (; s + 4 <= m; s += 4) {
+      int rc = launch_pass(c, (uint32_t)s, true, prop);
+      if (!rc) rc = launch_pass(c, (uint32_t)s + 2u, false, prop);
+      if (rc) return rc;
+    }
+  }
+  for (; s < m; ++s) {
+    int rc = launch_step(c, (uint32_t)s, (int)((c->t + s) & 1), prop);
     if (rc) return rc;
   }
   int rc = launch_advance(c, (uint64_t)m);
@@ -485,7 +587,8 @@ int alloc_meta(lb_ctx* c) {
   const size_t lats = sizeof(LatDesc) * nlat;
   const size_t blk = sizeof(uint32_t) * (nlat + 1);
   auto up = [](size_t v) { return (v + 255) & ~(size_t)255; };
-  const size_t total = head + up(part) + 2 * up(lats) + 2 * up(blk);
+  const size_t f2 = up(2 * sizeof(LatDesc));
+  const size_t total = head + up(part) + 2 * up(lats) + 2 * up(blk) + f2;
   HIP_TRY(hipMalloc(&c->d_meta, total));
   c->d_t = reinterpret_cast<uint64_t*>(c->d_meta);
   c->d_result = reinterpret_cast<double*>(c->d_meta + 64);
@@ -494,6 +597,7 @@ int alloc_meta(lb_ctx* c) {
   c->d_tile_lats = reinterpret_cast<LatDesc*>(c->d_meta + head + up(part) + up(lats));
   c->d_blk = reinterpret_cast<uint32_t*>(c->d_meta + head + up(part) + 2 * up(lats));
   c->d_blk_rows = reinterpret_cast<uint32_t*>(c->d_meta + head + up(part) + 2 * up(lats) + up(blk));
+  c->d_f2 = reinterpret_cast<LatDesc*>(c->d_meta + head + up(part) + 2 * up(lats) + 2 * up(blk));
   HIP_TRY(hipHostMalloc((void**)&c->h_result, sizeof(double) * 5, hipHostMallocDefault));
   HIP_TRY(hipMemcpy(c->d_lats, c->lats.data(), lats, hipMemcpyHostToDevice));
   return LB_OK;
@@ -503,6 +607,7 @@ void free_ctx(lb_ctx* c) {
   if (!c) return;
   if (c->owner) {
     drop_graph(c);
+    release_state_b(c);
     if (c->d_meta) (void)hipFree(c->d_meta);
     if (c->h_result) (void)hipHostFree(c->h_result);
   }
@@ -533,9 +638,9 @@ int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity
 // policy measured as fast or faster.  lb_autotune refines it for a given
 // workload.
 int default_schedule(lb_ctx* c) {
-  if (c->storage == LB_F32) c->sched = lb_schedule{256, 0, 16, {0, 0}, {1, 0}, 0, 0};
-  else if (c->lattice == LB_D2Q9) c->sched = lb_schedule{256, 0, 16, {0, 0}, {0, 1}, 0, 0};
-  else c->sched = lb_schedule{256, 0, 16, {8, 8}, {0, 1}, 0, 0};
+  if (c->storage == LB_F32) c->sched = lb_schedule{256, 0, 16, {0, 0}, {1, 0}, 0, 0, 0};
+  else if (c->lattice == LB_D2Q9) c->sched = lb_schedule{256, 0, 16, {0, 0}, {0, 1}, 0, 0, 0};
+  else c->sched = lb_schedule{256, 0, 16, {8, 8}, {0, 1}, 0, 0, 0};
   if (c->wide) c->sched.tiling[0] = c->sched.tiling[1] = 0;
   if (!c->wide) {
     uint64_t total = 0, largest = 0;
@@ -550,6 +655,16 @@ int default_schedule(lb_ctx* c) {
     } else if (total >= 32 * MB && largest <= 224 * MIB) {
       c->sched.resident = 1;
       c->sched.group_mb = 224;
+    }
+    // fp32 D3Q19 state beyond the cache streams through HBM: two fused steps
+    // per launch move about half the bytes (512^3: 5.2-5.4 against 7.2 ms
+    // per two steps), when the second buffer fits on the device.  The 16-bit
+    // forms keep one step per launch: their collision already keeps the VALU
+    // busy enough that the fused pass, with its halo collisions, is slower.
+    if (c->storage == LB_F32 && fused_eligible(c) && total > 320 * MB) {
+      const std::string keep = g_last_error;
+      if (ensure_state_b(c) == LB_OK) c->sched.fused = 1;
+      else g_last_error = keep;  // no room: one step per launch, not an error
     }
   }
   return upload_schedule(c);
@@ -642,6 +757,10 @@ int lb_init(const lb_params* p, void* d_state, void* hip_stream, int32_t init_ki
     free_ctx(c);
     return rc;
   }
+  if (p->storage == LB_BF16 && p->kT == 0.0)
+    g_last_error = "warning: bf16 storage without thermal noise is biased (its rounding of slowly varying "
+                   "fields does not average out: a shear wave decays about 2% too slowly); use fp16 or fp32 "
+                   "for deterministic runs";
   *out = c;
   return LB_OK;
 }
@@ -658,13 +777,19 @@ int lb_propagate(lb_ctx* ctx, int64_t nsteps) {
   if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
   if (nsteps == 0) return LB_OK;
   HIP_TRY(hipSetDevice(ctx->device));
-  for (int64_t s = 0; s < nsteps; ++s) {
-    int rc = launch_step(ctx, (uint32_t)s, (int)((ctx->t + s) & 1), true);
+  // the same launches as lb_step's direct path (fused passes under the fused
+  // schedule), with the propagation-only kernels
+  if (ctx->t & 1) {
+    int rc = direct_steps(ctx, 1, true);
     if (rc) return rc;
+    --nsteps;
   }
-  int rc = launch_advance(ctx, (uint64_t)nsteps);
-  if (rc) return rc;
-  ctx->t += nsteps;
+  while (nsteps > 0) {
+    const int64_t m = std::min<int64_t>(nsteps, 1024);
+    int rc = direct_steps(ctx, m, true);
+    if (rc) return rc;
+    nsteps -= m;
+  }
   return LB_OK;
 }
 
@@ -883,10 +1008,19 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s) {
   if (s->resident != 0 && s->resident != 1) return fail(LB_EINVAL, "resident must be 0 or 1");
   if (s->resident && ctx->wide) return fail(LB_EUNSUPPORTED, "the resident cache policy needs planes below 4 GiB");
   if (s->group_mb < 0 || s->group_mb > (1 << 20)) return fail(LB_EINVAL, "group_mb must be in [0, 2^20]");
+  if (s->fused != 0 && s->fused != 1) return fail(LB_EINVAL, "fused must be 0 or 1");
+  if (s->fused && !fused_eligible(ctx))
+    return fail(LB_EUNSUPPORTED, "the fused schedule needs a single D3Q19 lattice with planes below 4 GiB");
 
   HIP_TRY(hipSetDevice(ctx->device));
+  if (s->fused) {
+    int rc = ensure_state_b(ctx);
+    if (rc) return rc;
+  }
   ctx->sched = *s;
-  return upload_schedule(ctx);
+  int rc = upload_schedule(ctx);
+  if (!s->fused) release_state_b(ctx);
+  return rc;
 }
 
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
@@ -900,6 +1034,13 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   size_t bytes = 0;
   for (size_t r = 0; r < ctx->reps.size(); ++r)
     bytes = std::max<size_t>(bytes, ctx->offsets[r] + ((lb_state_bytes(&ctx->reps[r]) + 255) & ~(size_t)255));
+  {
+    // a predictable failure is reported as such, before anything changes
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    if (free_b < bytes + (256ull << 20))
+      return fail(LB_EUNSUPPORTED, "not enough free device memory for the autotuner's scratch copy of the state");
+  }
   char* scratch = nullptr;
   HIP_TRY(hipMalloc(&scratch, bytes));
   const uint64_t base0 = ctx->lats[0].base - ctx->offsets[0];
@@ -1018,7 +1159,7 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   // rounds.  A variant replaces the first stage's choice (streaming, one
   // group) only when it is at least 1% faster.
   struct Var {
-    int res, gmb;
+    int res, gmb, fused;
     double ms;
   };
   std::vector<Var> vars;
@@ -1026,7 +1167,13 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
     const int gmbs[] = {0, 64, 128, 160, 192, 224, 256};
     const int ngmb = ctx->lats.size() > 1 ? 7 : 1;
     for (int res = 0; res < (ctx->wide ? 1 : 2); ++res)
-      for (int gi = 0; gi < ngmb; ++gi) vars.push_back({res, gmbs[gi], 0.0});
+      for (int gi = 0; gi < ngmb; ++gi) vars.push_back({res, gmbs[gi], 0, 0.0});
+    // the fused two-step schedule, when its second buffer fits
+    if (rc == LB_OK && fused_eligible(ctx)) {
+      const std::string keep = g_last_error;
+      if (ensure_state_b(ctx) == LB_OK) vars.push_back({0, 0, 1, 0.0});
+      else g_last_error = keep;
+    }
   }
   const int K2 = best.graph_chunk;
   const int64_t chunks = std::max<int64_t>(1, (2 * (int64_t)steps + K2 - 1) / K2);
@@ -1034,6 +1181,7 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
     ctx->sched = best;
     ctx->sched.resident = v.res;
     ctx->sched.group_mb = v.gmb;
+    ctx->sched.fused = v.fused;
     int r = upload_schedule(ctx);
     if (r == LB_OK && (ctx->t & 1)) r = direct_steps(ctx, 1);
     if (r == LB_OK) r = advance(ctx, K2);  // warm-up replay (builds the graph)
@@ -1060,6 +1208,7 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
       if (v.ms < pick->ms && v.ms < 0.99 * vars[0].ms) pick = &v;
     best.resident = pick->res;
     best.group_mb = pick->gmb;
+    best.fused = pick->fused;
   }
 
   std::string rep = "[";
@@ -1079,8 +1228,8 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   for (const auto& v : vars) {
     if (vars.size() < 2 || rc != LB_OK) break;
     char buf[160];
-    std::snprintf(buf, sizeof(buf), ",{\"stage\":2,\"resident\":%d,\"group_mb\":%d,\"ms_per_step\":%.6f}", v.res,
-                  v.gmb, v.ms);
+    std::snprintf(buf, sizeof(buf), ",{\"stage\":2,\"resident\":%d,\"group_mb\":%d,\"fused\":%d,\"ms_per_step\":%.6f}",
+                  v.res, v.gmb, v.fused, v.ms);
     rep += buf;
   }
   rep += "]";
@@ -1096,6 +1245,7 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   hipLaunchKernelGGL(k_set_t, dim3(1), dim3(64), 0, ctx->stream, ctx->d_t, (uint64_t)saved_t);
   ctx->sched = (rc == LB_OK) ? best : saved;
   int rc2 = upload_schedule(ctx);
+  if (!ctx->sched.fused) release_state_b(ctx);
   if (report && report_len) {
     std::strncpy(report, rep.c_str(), report_len - 1);
     report[report_len - 1] = 0;

@@ -681,6 +681,198 @@ k_propagate_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------- two fused steps
+// k_step2 advances a D3Q19 lattice by two steps, t and t + 1 (t even), in one
+// pass over HBM: it reads the state in the even AA layout (plane i at site r
+// holds n_i(r)) from one buffer and writes the state at t + 2, in the same
+// layout, to a second buffer.  Each population of the lattice is read once
+// (plus a one-site halo) and written once per two steps instead of twice.
+//
+// Work split.  A workgroup owns a 64 x F2_TY column of x-y sites and walks a
+// chunk of zlen planes along z.  Its waves 0..F2_TY-1 hold one x-row each;
+// two more waves hold the halo rows y0 - 1 and y0 + F2_TY, and one the halo
+// columns x0 - 1 and x0 + 64 (periodic).  For each plane the first step is
+// collided on the tile and its halo, and every post-collision population
+// that lands inside the tile is pushed into an LDS ring that accumulates the
+// pre-collision populations of the second step: the c_z = -1 populations of
+// plane u belong to plane u - 1, c_z = 0 to u, c_z = +1 to u + 1.  The second
+// step of plane u - 2 is then collided from the ring (its last populations
+// arrived one plane earlier) and pushed along c_j into the destination
+// buffer.  Both steps of one plane share a phase, with one barrier per plane;
+// the ring keeps flat populations for 3 planes, up-going for 4 and
+// down-going for 2 (57 planes of 64 x F2_TY values).  The loads of the next
+// plane but one are in flight while a plane is processed.
+//
+// The two steps compute exactly what two k_step launches compute (same
+// collision code, same noise keys, 16-bit values rounded into the ring as
+// they would be stored), so the result is bit-identical to the AA pair.
+// PROP: the identity collision (the data-movement floor of the pass).
+constexpr int F2_TY = 10;                     // interior rows per tile
+constexpr int F2_THREADS = (F2_TY + 3) * 64;  // interior + two halo-row + one halo-column waves
+
+template <class M> struct ZClass {
+  // index of population i among the populations with its c_z
+  static constexpr int idx(int i) {
+    int n = 0;
+    for (int j = 0; j < i; ++j) n += (M::CZ[j] == M::CZ[i]) ? 1 : 0;
+    return n;
+  }
+};
+
+struct F2Ring {
+  static constexpr int TP = 64 * F2_TY;          // interior sites of a tile
+  static constexpr int NF = 9, NU = 5, ND = 5;   // D3Q19 populations with c_z = 0, +1, -1
+  static constexpr int SF = 3, SU = 4, SD = 2;   // ring slots (planes in flight) per class
+  static constexpr int BASE_U = SF * NF * TP;
+  static constexpr int BASE_D = BASE_U + SU * NU * TP;
+  static constexpr int TOTAL = BASE_D + SD * ND * TP;
+  // element offset of population i's plane in the slots (fs, us, ds)
+  static __device__ __forceinline__ uint32_t base(int i, uint32_t fs, uint32_t us, uint32_t ds) {
+    const int c = D3Q19::CZ[i];
+    const uint32_t k = (uint32_t)ZClass<D3Q19>::idx(i) * TP;
+    if (c == 0) return fs * (NF * TP) + k;
+    if (c > 0) return BASE_U + us * (NU * TP) + k;
+    return BASE_D + ds * (ND * TP) + k;
+  }
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc_base(uint64_t base, uint64_t plane_elems, int plane,
+                                                                  uint32_t esize) {
+  const uint64_t bytes = plane_elems * esize;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)(base + (uint64_t)plane * bytes), 0,
+                                           (int)(uint32_t)bytes, RAW_BUFFER_WORD3);
+}
+
+template <int S, bool PROP>
+__global__ void __launch_bounds__(F2_THREADS)
+k_step2(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* __restrict__ d_t, uint32_t t_off,
+        uint32_t ntx, uint32_t nty, uint32_t zlen) {
+  using M = D3Q19;
+  using C = Codec<S>;
+  using T = typename C::T;
+  using R = F2Ring;
+  constexpr int Q = M::Q;
+  constexpr uint32_t ES = sizeof(T);
+  __shared__ T ring[R::TOTAL];
+  const LatDesc& L = *src;
+
+  // tile: each XCD takes one contiguous eighth of the tiles (x fastest, then
+  // y, then z chunk), so the tiles sharing halo lines run on one L2
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x, 1);
+  const uint32_t txi = b % ntx, rest = b / ntx;
+  const uint32_t tyi = rest % nty, tzi = rest / nty;
+  const uint32_t nx = L.nx, ny = L.ny, nz = L.nz, nxy = L.nxy;
+  const uint32_t x0 = txi * 64u, y0 = tyi * (uint32_t)F2_TY, z0 = tzi * zlen;
+  const uint32_t TW = min(64u, nx - x0), TH = min((uint32_t)F2_TY, ny - y0), ZC = min(zlen, nz - z0);
+  const uint32_t NIT = ZC + 3u;  // phase it: first step of plane z0 + it - 1, second of z0 + it - 3
+  const uint32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+  const uint64_t t = *d_t + t_off;
+
+  // first-step site of this lane, in tile coordinates sx in [-1, TW], sy in [-1, TH]
+  int sx, sy;
+  bool act1;
+  if (w < (uint32_t)F2_TY) {
+    sx = (int)lane; sy = (int)w; act1 = lane < TW && w < TH;
+  } else if (w == (uint32_t)F2_TY) {
+    sx = (int)lane; sy = -1; act1 = lane < TW;
+  } else if (w == (uint32_t)F2_TY + 1u) {
+    sx = (int)lane; sy = (int)TH; act1 = lane < TW;
+  } else {
+    const uint32_t h = lane & 31u;
+    sx = lane < 32u ? -1 : (int)TW; sy = (int)h - 1; act1 = h < TH + 2u;
+  }
+  const int gx = (int)x0 + sx, gy = (int)y0 + sy;
+  const uint32_t x1 = gx < 0 ? nx - 1u : ((uint32_t)gx >= nx ? 0u : (uint32_t)gx);
+  const uint32_t y1 = gy < 0 ? ny - 1u : ((uint32_t)gy >= ny ? 0u : (uint32_t)gy);
+  const uint32_t sxy = x1 + nx * y1;
+  const int s1idx = sy * 64 + sx;  // ring index of the first-step site (when inside the tile)
+
+  // second-step site of this lane (interior waves); periodic neighbour offsets
+  const bool act2 = w < TH && lane < TW;
+  const uint32_t x2 = x0 + lane, y2 = y0 + w;
+  const uint32_t bx = x2 * ES;
+  const uint32_t bxm = (x2 == 0 ? nx - 1u : x2 - 1u) * ES;
+  const uint32_t bxp = (x2 + 1u >= nx ? 0u : x2 + 1u) * ES;
+  const uint32_t ry = y2 * nx;
+  const uint32_t rym = (y2 == 0 ? ny - 1u : y2 - 1u) * nx;
+  const uint32_t ryp = (y2 + 1u >= ny ? 0u : y2 + 1u) * nx;
+  const uint32_t lidx = w * 64u + lane;
+
+  auto zfirst = [&](uint32_t it) {  // lattice z of the first-step plane of phase it
+    const int zz = (int)z0 + (int)it - 1;
+    return zz < 0 ? nz - 1u : ((uint32_t)zz >= nz ? 0u : (uint32_t)zz);
+  };
+  auto load_plane = [&](uint32_t it, T (&v)[Q]) {
+    const uint32_t so = zfirst(it) * nxy * ES;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = Raw<T>::template ld<0>(plane_rsrc(L, i, ES), sxy * ES, so);
+  };
+  // first step of plane u = it - 1: collide, push into P(u - 1), P(u), P(u + 1)
+  auto first = [&](uint32_t it, const T (&v)[Q]) {
+    if (!act1 || it > ZC + 1u) return;
+    float d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = C::dec(v[i]);
+    if constexpr (!PROP) collide<M>(L, d, sxy + zfirst(it) * nxy, (uint32_t)t, (uint32_t)(t >> 32));
+    const uint32_t fs = (it + 2u) % 3u, us = it % 4u, ds = it & 1u;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int tx = sx + M::CX[i], ty = sy + M::CY[i];
+      if (tx >= 0 && tx < (int)TW && ty >= 0 && ty < (int)TH)
+        ring[R::base(i, fs, us, ds) + (uint32_t)(s1idx + M::CY[i] * 64 + M::CX[i])] = PROP ? v[i] : C::enc(d[i]);
+    }
+  };
+  // second step of plane z0 + it - 3 from P(it - 3), pushed into the destination
+  auto second = [&](uint32_t it) {
+    if (it < 3u || !act2) return;
+    const uint32_t z = z0 + it - 3u;
+    const uint32_t fs = it % 3u, us = (it + 1u) % 4u, ds = (it + 1u) & 1u;
+    T h[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) h[i] = ring[R::base(i, fs, us, ds) + lidx];
+    float d[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = C::dec(h[i]);
+    if constexpr (!PROP) {
+      const uint64_t t1 = t + 1u;
+      collide<M>(L, d, x2 + ry + z * nxy, (uint32_t)t1, (uint32_t)(t1 >> 32));
+    }
+    const uint32_t rz = z * nxy;
+    const uint32_t rzm = (z == 0 ? nz - 1u : z - 1u) * nxy;
+    const uint32_t rzp = (z + 1u >= nz ? 0u : z + 1u) * nxy;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const uint32_t ro = (M::CY[j] > 0 ? ryp : (M::CY[j] < 0 ? rym : ry)) +
+                          (M::CZ[j] > 0 ? rzp : (M::CZ[j] < 0 ? rzm : rz));
+      const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
+      const T v = PROP ? h[j] : C::enc(d[j]);
+      // x-shifted planes share lines with the neighbouring tiles: cached; the others stream
+      if (M::CX[j] != 0) Raw<T>::template st<0>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
+      else Raw<T>::template st<CPOL_NT>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
+    }
+  };
+
+  // two planes of loads in flight (register sets a and c, unrolled by two so
+  // that both stay in registers); the first and second steps of a phase touch
+  // different ring slots, so one barrier per phase suffices
+  T a[Q], c[Q];
+  if (act1) {
+    load_plane(0u, a);
+    load_plane(1u, c);
+  }
+  for (uint32_t it = 0; it < NIT; it += 2u) {
+    first(it, a);
+    if (act1 && it + 2u <= ZC + 1u) load_plane(it + 2u, a);
+    second(it);
+    __syncthreads();
+    if (it + 1u >= NIT) break;
+    first(it + 1u, c);
+    if (act1 && it + 3u <= ZC + 1u) load_plane(it + 3u, c);
+    second(it + 1u);
+    __syncthreads();
+  }
+}
+
 // Advance the device step counter after a run of step kernels.
 __global__ void k_advance(uint64_t* d_t, uint64_t n) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *d_t += n;

@@ -6,6 +6,7 @@ no GPU is present, the calls raise: there is no fallback path.
 """
 import ctypes
 import os
+import warnings
 
 import torch
 
@@ -36,13 +37,13 @@ class LbParams(ctypes.Structure):
 class LbSchedule(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("order", ctypes.c_int32), ("graph_chunk", ctypes.c_int32),
                 ("xcd_remap", ctypes.c_int32 * 2), ("tiling", ctypes.c_int32 * 2),
-                ("resident", ctypes.c_int32), ("group_mb", ctypes.c_int32)]
+                ("resident", ctypes.c_int32), ("group_mb", ctypes.c_int32), ("fused", ctypes.c_int32)]
 
 
 def _sched_dict(s):
     return {"block": s.block, "order": s.order, "graph_chunk": s.graph_chunk,
             "xcd_remap": list(s.xcd_remap), "tiling": list(s.tiling),
-            "resident": s.resident, "group_mb": s.group_mb}
+            "resident": s.resident, "group_mb": s.group_mb, "fused": s.fused}
 
 
 def _pair(v):
@@ -52,9 +53,9 @@ def _pair(v):
     return (ctypes.c_int32 * 2)(int(v), int(v))
 
 
-def _make_schedule(block, order, xcd_remap, graph_chunk, tiling, resident=0, group_mb=0):
+def _make_schedule(block, order, xcd_remap, graph_chunk, tiling, resident=0, group_mb=0, fused=0):
     return LbSchedule(int(block), int(order), int(graph_chunk), _pair(xcd_remap), _pair(tiling),
-                      int(resident), int(group_mb))
+                      int(resident), int(group_mb), int(fused))
 
 
 # (name, restype, argtypes) of every entry point in include/lbf.h
@@ -263,6 +264,8 @@ class Lattice(_Gathers):
         _check(lib().lb_init(ctypes.byref(self.params), _aligned(self.state), sp, INIT[init], f,
                              int(t0), ctypes.byref(ctx)), "lb_init")
         self._ctx = ctx
+        if storage == "bf16" and kT == 0:
+            warnings.warn(lib().lb_last_error().decode(), stacklevel=2)
 
     def step(self, n=1):
         _check(lib().lb_step(self._ctx, int(n)), "lb_step")
@@ -276,11 +279,14 @@ class Lattice(_Gathers):
         _check(lib().lb_get_schedule(self._ctx, ctypes.byref(s)), "lb_get_schedule")
         return _sched_dict(s)
 
-    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0, resident=0, group_mb=0):
+    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0, resident=0, group_mb=0,
+                     fused=0):
         """xcd_remap and tiling: an int for both step parities or an
         (even, odd) pair; resident: cache every access (1) or stream (0);
-        group_mb: replica groups of at most this many MiB of state (0: one)."""
-        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling, resident, group_mb)
+        group_mb: replica groups of at most this many MiB of state (0: one);
+        fused: two steps per launch through a second buffer (1) or one
+        in-place step per launch (0)."""
+        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling, resident, group_mb, fused)
         _check(lib().lb_set_schedule(self._ctx, ctypes.byref(s)), "lb_set_schedule")
 
     def autotune(self, steps=10):
@@ -383,11 +389,14 @@ class Ensemble:
         _check(lib().lb_get_schedule(self._ctx, ctypes.byref(s)), "lb_get_schedule")
         return _sched_dict(s)
 
-    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0, resident=0, group_mb=0):
+    def set_schedule(self, block=256, order=0, xcd_remap=1, graph_chunk=16, tiling=0, resident=0, group_mb=0,
+                     fused=0):
         """xcd_remap and tiling: an int for both step parities or an
         (even, odd) pair; resident: cache every access (1) or stream (0);
-        group_mb: replica groups of at most this many MiB of state (0: one)."""
-        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling, resident, group_mb)
+        group_mb: replica groups of at most this many MiB of state (0: one);
+        fused: two steps per launch through a second buffer (1) or one
+        in-place step per launch (0)."""
+        s = _make_schedule(block, order, xcd_remap, graph_chunk, tiling, resident, group_mb, fused)
         _check(lib().lb_set_schedule(self._ctx, ctypes.byref(s)), "lb_set_schedule")
 
     def autotune(self, steps=10):

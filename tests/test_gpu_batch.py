@@ -297,7 +297,8 @@ def test_default_schedule_cache_policy():
     """The default schedule runs state that fits in the Infinity Cache
     resident: a single lattice of 32-320 MB, and a batch of 32 MB or more
     whose replicas each fit in 224 MiB (then in 224 MiB groups); tiny state
-    and batches with a larger replica stream."""
+    and batches with a larger replica stream.  An fp32 lattice beyond the
+    cache takes the fused two-step pass."""
     base = dict(rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=0.0, gamma_even=0.0, seed=9)
     cases = [(dict(nx=48, ny=48, nz=48), "f32", (0, 0)),       # 8.4 MB
              (dict(nx=128, ny=128, nz=128), "f32", (1, 0)),    # 159 MB
@@ -307,6 +308,7 @@ def test_default_schedule_cache_policy():
         lat = lbf.Lattice(**dims, **base, storage=st, init="rest")
         s = lat.schedule()
         assert (s["resident"], s["group_mb"]) == want, (dims, st, s)
+        assert s["fused"] == (1 if (st == "f32" and dims["nx"] == 192) else 0), (dims, st, s)
         lat.close()
     four = [dict(base, nx=96, ny=96, nz=96, seed=s) for s in range(4)]          # 4 x 67 MB
     ens = lbf.Ensemble(four, init="rest")

@@ -47,7 +47,7 @@ def test_invalid_schedules_rejected():
     before = lat.schedule()
     for bad in [dict(block=96), dict(order=3), dict(graph_chunk=3), dict(graph_chunk=0), dict(xcd_remap=65), dict(xcd_remap=-1),
                 dict(tiling=(0, 5)), dict(resident=2), dict(resident=-1), dict(group_mb=-1),
-                dict(group_mb=(1 << 20) + 1)]:
+                dict(group_mb=(1 << 20) + 1), dict(fused=2), dict(fused=-1)]:
         args = dict(block=256, order=0, xcd_remap=0, graph_chunk=16, tiling=0)
         args.update(bad)
         with pytest.raises(lb.LBError) as ei:
@@ -87,3 +87,33 @@ def test_init_argument_errors_on_device():
     assert L.lb_init(ctypes.byref(p), ctypes.c_void_p(buf.data_ptr()), None, 2, None, 0,
                      ctypes.byref(ctx)) == lb.LB_EINVAL
     assert ctx.value is None
+
+
+def test_bf16_without_noise_warns():
+    with pytest.warns(UserWarning, match="bf16 storage without thermal noise is biased"):
+        lat = lbf.Lattice(nx=8, ny=8, nz=8, storage="bf16", kT=0.0, init="rest")
+    assert "warning: bf16" in lb.lib().lb_last_error().decode()
+    lat.close()
+
+
+def test_autotune_without_room_for_its_scratch_copy():
+    """The autotuner needs a scratch copy of the state: with less free device
+    memory than that it returns LB_EUNSUPPORTED and changes nothing."""
+    lat = lbf.Lattice(nx=512, ny=512, nz=256, storage="f32", kT=1e-4, seed=3, init="thermal")  # 5.1 GB
+    lat.set_schedule(block=256, xcd_remap=0, graph_chunk=16, tiling=0)
+    before = lat.schedule()
+    state = lat.state.clone()
+    torch.cuda.synchronize()
+    free = torch.cuda.mem_get_info()[0]
+    filler = torch.empty(max(free - (2 << 30), 0), dtype=torch.uint8, device="cuda")  # leave 2 GiB free
+    try:
+        with pytest.raises(lb.LBError) as ei:
+            lat.autotune(steps=2)
+        assert ei.value.code == lb.LB_EUNSUPPORTED
+        assert "scratch copy" in str(ei.value)
+    finally:
+        del filler
+        torch.cuda.empty_cache()
+    assert lat.schedule() == before and lat.t == 0
+    assert torch.equal(lat.state, state)
+    lat.close()
