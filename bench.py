@@ -11,12 +11,17 @@ step and replica group, autotuned), and the D2Q9 lattice (Table I) on a
 16384^2 box (2^28 sites) with fp32 and bf16 storage.
 
 Prints one JSON line.  `value` is MLUPS (million lattice-site updates per
-second) of the fp32 run with the state resident in HBM; `roofline` compares
-the step kernel's algorithmic bytes (19 populations read and written, 2 * 19
-* 4 bytes per site) per launch, divided by the mean launch duration measured
-with HIP events on the kernel's stream, with the 8 TB/s HBM peak; the mode
-variances of the final state are checked against mu rho w_k (the stationary
-law), and `cpu_baseline` times the FP64 CPU oracle on a bounded sample.
+second) of the fp32 run with the state resident in HBM, timed with HIP events
+over the whole timed region.  `roofline` is about the dominant kernel of that
+run: its algorithmic bytes per launch (19 populations read and written per
+site-update, 2 * 19 * 4 bytes, times the site-updates one launch performs:
+two per site for the fused two-step pass) divided by its mean launch
+duration, measured with HIP events on the lattice's stream around direct
+launches after the timed region, against the 8 TB/s HBM peak; `traffic` is
+the HBM bytes per launch counted by the profiler (stored with the kernel
+sources' hash).  The mode variances of the final state are checked against
+mu rho w_k (the stationary law), and `cpu_baseline` times the FP64 CPU
+oracle on a bounded sample.
 """
 import argparse
 import hashlib
@@ -33,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 W36 = [36, 12, 12, 12, 24, 48, 16, 4, 4, 4, 24, 24, 24, 8, 8, 8, 72, 48, 16]  # 36 w_k, Table II
 W36_D2Q9 = [36, 12, 12, 144, 16, 4, 24, 24, 576]  # 36 w_k, Table I
 KERNEL_SOURCES = ["paper_0707_1581_amd/csrc/lbf_kernels.h", "paper_0707_1581_amd/csrc/lbf_math.h"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_aa_step_512.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_512.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_step.json")
 # VALU issue budget: 256 CUs x 4 SIMDs at 2.4 GHz; a wave64 fp32 add/mul/fma issues in 2 cycles,
 # conversions and integer multiplies in 4, transcendentals in 8 (measured on gfx950)
@@ -54,9 +59,11 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(storage):
-    """HBM bytes per step launch measured by rocprofv3 counters (FETCH_SIZE +
-    WRITE_SIZE, scaled by a copy kernel), if taken on the current kernel."""
+def stored_traffic(key):
+    """HBM bytes per launch of the dominant kernel of a run (key: storage,
+    with "_fused" for the fused two-step pass) measured by rocprofv3
+    counters (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel), if taken on
+    the current kernel sources."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -64,7 +71,7 @@ def stored_traffic(storage):
         return None
     if rec.get("kernel_hash") != kernel_hash():
         return None
-    return rec.get("bytes_per_launch", {}).get(storage)
+    return rec.get("bytes_per_launch", {}).get(key)
 
 
 def stored_valu(key, mlups):
@@ -87,6 +94,37 @@ def stored_valu(key, mlups):
     busy = cyc * mlups * 1e6 / 64 / VALU_SIMD_CYCLES
     return {"instr_per_site": ips, "issue_cycles_per_wave": cyc, "busy_frac": busy,
             "source": "profiles/k_step_valu.md"}
+
+
+def progress(msg):
+    """A progress line on stderr (stdout carries only the result line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def launch_duration(lat, reps=10):
+    """Mean duration (ms) of one launch of the run's step kernel, from HIP
+    events on the lattice's stream around direct (never graph-replayed)
+    calls: under the fused schedule lb_step(4) from even t is two k_step2
+    launches, otherwise lb_step(2) is one even and one odd AA launch; each
+    call also runs the 1-thread step-counter advance (a few microseconds)."""
+    import torch
+    fused = lat.schedule()["fused"] == 1
+    n = 4 if fused else 2
+    if lat.t % 2:
+        lat.step(1)
+    lat.step(n)  # warm-up
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+    for r in range(reps):
+        ev[2 * r].record(lat.stream)
+        lat.step(n)
+        ev[2 * r + 1].record(lat.stream)
+    torch.cuda.synchronize()
+    ms = sum(ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(reps)) / reps / 2
+    return {"kernel": ("k_step2<fp32/fp16/bf16> (fused pair of steps)" if fused else
+                       "k_step / k_step_rows (even and odd AA steps, as scheduled)"),
+            "ms": ms, "site_updates_per_launch_per_site": 2 if fused else 1,
+            "launches_timed": 2 * reps, "method": f"HIP events around {reps} direct lb_step({n}) calls"}
 
 
 def time_steps(step, steps, warmup, sync_stream):
@@ -147,7 +185,9 @@ def mode_variance_dev(lat, rho0, kT, lattice="d3q19"):
     return max(abs(r - 1.0) for r in mode_ratios(lat, rho0, kT, lattice))
 
 
-def run_lattice(dims, storage, steps, warmup, cfg, check=True, tune=True, lattice="d3q19"):
+def run_lattice(dims, storage, steps, warmup, cfg, check=True, tune=True, lattice="d3q19", single_step=False):
+    """single_step: keep one in-place AA launch per step (the single-buffer
+    schedule), whatever the default or the autotuner would choose."""
     import torch
     import paper_0707_1581_amd as lbf
     nx, ny, nz = dims
@@ -155,25 +195,34 @@ def run_lattice(dims, storage, steps, warmup, cfg, check=True, tune=True, lattic
     sites = nx * ny * nz
     if tune:  # on a scratch copy of the state, outside the timed region
         lat.autotune(steps=10)
+    if single_step and lat.schedule()["fused"]:
+        sc = lat.schedule()
+        sc["fused"] = 0
+        lat.set_schedule(**sc)
     ms = time_steps(lat.step, steps, warmup, lat.stream)
     bpe = 4 if storage == "f32" else 2
-    alg = 2 * lat.q * bpe * sites  # algorithmic bytes per step launch
+    alg = 2 * lat.q * bpe * sites  # algorithmic bytes per step (per site-update: 2 q s)
     out = dict(storage=storage, ms_per_step=ms, mlups=sites / ms / 1e3,
-               achieved_gbs=alg / ms / 1e6, alg_bytes_per_launch=alg, schedule=lat.schedule())
+               achieved_gbs=alg / ms / 1e6, alg_bytes_per_step=alg, schedule=lat.schedule())
+    launch = launch_duration(lat)
+    launch["alg_bytes_per_launch"] = alg * launch["site_updates_per_launch_per_site"]
+    launch["achieved_gbs"] = launch["alg_bytes_per_launch"] / launch["ms"] / 1e6
+    out["launch"] = launch
     out["valu"] = stored_valu(f"{lattice}_{storage}", out["mlups"])
     if check:
         nb, sums = lat.check()
         out["bad_sites"] = nb
         out["mode_variance_max_dev"] = mode_variance_dev(lat, cfg["rho0"], cfg["kT"], lattice)
     # the data-movement floor of the same box and schedule: propagation-only
-    # steps (the same tiles, accesses and cache policy, no collision), timed
-    # after the checks
+    # steps (the same launches, tiles, accesses and cache policy, no
+    # collision: fused passes under the fused schedule), timed after the checks
     pm = time_steps(lat.propagate, min(steps, 40), 4, lat.stream)
     out["propagate_only"] = {"ms_per_step": pm, "achieved_gbs": alg / pm / 1e6,
                              "step_speed_frac": pm / ms}
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    progress(f"{lattice} {nx}x{ny}x{nz} {storage}: {out['mlups']:.0f} MLUPS, schedule {out['schedule']}")
     return out
 
 
@@ -216,6 +265,7 @@ def run_ensemble(storage, steps, warmup):
     ens.close()
     del ens
     torch.cuda.empty_cache()
+    progress(f"ensemble of {len(reps)} {storage}: {out['mlups']:.0f} MLUPS aggregate")
     return out
 
 
@@ -383,6 +433,10 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--box", type=int, default=512)
+    ap.add_argument("--storage", choices=["f32", "f16", "bf16"], default="f32",
+                    help="storage of the main run (profiling runs; the benchmark line is fp32)")
+    ap.add_argument("--single-step", action="store_true",
+                    help="main run with one in-place AA launch per step (profiling runs)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-variants", action="store_true", help="time only the fp32 box")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedule")
@@ -412,9 +466,15 @@ def main():
     cfg = {k: workloads.LARGE[k] for k in ("rho0", "kT", "gamma_bulk", "gamma_shear", "gamma_odd",
                                           "gamma_even", "seed")}
     box3 = (args.box, args.box, args.box)
-    main_run = run_lattice(box3, "f32", args.steps, args.warmup, cfg, tune=not args.no_tune)
+    main_run = run_lattice(box3, args.storage, args.steps, args.warmup, cfg, tune=not args.no_tune,
+                           single_step=args.single_step)
     variants = {}
     if not args.no_variants:
+        # the same box with one in-place AA launch per step (a single state buffer)
+        r = run_lattice(box3, "f32", args.steps, args.warmup, cfg, tune=not args.no_tune, single_step=True)
+        r["roofline_frac"] = r["achieved_gbs"] / HBM_PEAK_GBS
+        r["workload"] = "the main box and parameters, fp32, one in-place AA launch per step (single 10.2 GB buffer)"
+        variants["f32_single_step"] = r
         for st in ("f16", "bf16"):
             r = run_lattice(box3, st, args.steps, args.warmup, cfg, tune=not args.no_tune)
             r["roofline_frac"] = r["achieved_gbs"] / HBM_PEAK_GBS
@@ -442,22 +502,37 @@ def main():
     if args.copy_calibration:
         copy_calibration()
 
-    traffic = stored_traffic("f32")
-    roofline = {"bound": "hbm", "achieved": main_run["achieved_gbs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": main_run["achieved_gbs"] / HBM_PEAK_GBS,
+    fused = main_run["schedule"]["fused"] == 1
+    L = main_run["launch"]
+    traffic = stored_traffic(args.storage + ("_fused" if fused else ""))
+    roofline = {"bound": "hbm", "achieved": L["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": L["achieved_gbs"] / HBM_PEAK_GBS,
                 "traffic": traffic,
-                "kernel": "fp32 step kernel (lbf::k_step / lbf::k_step_rows as scheduled; even and odd "
-                          "AA launches; mean launch duration)",
-                "alg_bytes_per_launch": main_run["alg_bytes_per_launch"]}
+                "kernel": L["kernel"],
+                "launch_ms": L["ms"],
+                "launch_timing": L["method"] + ", on the lattice's stream, after the timed region",
+                "alg_bytes_per_launch": L["alg_bytes_per_launch"],
+                "alg_bytes_per_site_update": 2 * 19 * (4 if args.storage == "f32" else 2),
+                "site_updates_per_launch": L["site_updates_per_launch_per_site"] * args.box ** 3}
+    if traffic:
+        roofline["traffic_gbs"] = traffic / L["ms"] / 1e6
+        roofline["traffic_frac"] = roofline["traffic_gbs"] / HBM_PEAK_GBS
+        roofline["traffic_over_alg"] = traffic / L["alg_bytes_per_launch"]
+    if fused:
+        roofline["note"] = ("two site-updates per launch: each population is read once (with a one-site halo) and "
+                            "written once per two updates, so the algorithmic rate can pass the device copy rate; "
+                            "traffic_gbs is the HBM rate actually moved")
     # two references for the step's HBM rate, measured on this device: the
     # library's float4 non-temporal copy (the practical streaming ceiling) and
     # the same launches as the timed step without the collision (lb_propagate,
-    # same schedule, accesses and cache policy)
+    # same schedule, accesses and cache policy).  The rates are algorithmic
+    # (2 q s bytes per site-update), so under the fused schedule, which moves
+    # about half of those bytes, they can pass the copy rate.
     from paper_0707_1581_amd import lb as lbmod
     copy_gbs = lbmod.copy_rate(gib=4, reps=10)
     prop = main_run["propagate_only"]
     ceilings = {"device_copy_gbs": copy_gbs, "device_copy_frac_of_peak": copy_gbs / HBM_PEAK_GBS,
-                "step_frac_of_device_copy": main_run["achieved_gbs"] / copy_gbs,
+                "alg_rate_over_device_copy": main_run["achieved_gbs"] / copy_gbs,
                 "propagate_only_ms_per_step": prop["ms_per_step"], "propagate_only_gbs": prop["achieved_gbs"],
                 "propagate_only_frac_of_peak": prop["achieved_gbs"] / HBM_PEAK_GBS,
                 "step_speed_frac_of_propagate_only": prop["ms_per_step"] / main_run["ms_per_step"]}
@@ -472,12 +547,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.storage,
         "data": "synthetic",
-        "config": {"workload": f"D3Q19 fluctuating LB, {args.box}^3 periodic box, fp32 AA in-place single "
-                               f"buffer, rho0=1, kT=1e-4, gamma_shear=0.8, gamma_bulk=0.5, kinetic rates 0, "
-                               f"thermal start, Philox seed 1234",
-                   "sites": args.box ** 3, "storage": "f32",
+        "config": {"workload": f"D3Q19 fluctuating LB, {args.box}^3 periodic box, {args.storage} storage, rho0=1, "
+                               f"kT=1e-4, gamma_shear=0.8, gamma_bulk=0.5, kinetic rates 0, thermal start, Philox "
+                               f"seed 1234; "
+                               + ("fused two-step passes through a second state buffer (the library's default and "
+                                  "autotuned schedule for this box; the single-buffer AA schedule is the "
+                                  "f32_single_step variant)" if fused else "AA in-place single buffer"),
+                   "sites": args.box ** 3, "storage": args.storage,
                    "mode_variance_max_dev": main_run["mode_variance_max_dev"],
                    "bad_sites": main_run["bad_sites"], "schedule": main_run["schedule"]},
         "roofline": roofline,
