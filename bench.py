@@ -76,11 +76,12 @@ def stored_traffic(key):
 
 def stored_valu(key, mlups):
     """VALU figures of a run: instructions per site-update from the
-    SQ_INSTS_VALU counter and issue cycles per wave (the instruction mix of
-    the gfx950 assembly weighted by measured issue costs), both stored with
-    the kernel-source hash as the mean of the default schedule's even and
-    odd kernels, and the fraction of the VALU issue cycles the measured
-    site-update rate keeps busy."""
+    SQ_INSTS_VALU counter and issue cycles per wave of 64 site-updates (the
+    counted instruction mix weighted by measured issue costs), both stored
+    with the kernel-source hash (AA schedules: the mean of the default
+    schedule's even and odd kernels; key suffix "_fused": the fused pass),
+    and the fraction of the VALU issue cycles the measured site-update rate
+    keeps busy."""
     try:
         with open(VALU_FILE) as f:
             rec = json.load(f)
@@ -208,7 +209,7 @@ def run_lattice(dims, storage, steps, warmup, cfg, check=True, tune=True, lattic
     launch["alg_bytes_per_launch"] = alg * launch["site_updates_per_launch_per_site"]
     launch["achieved_gbs"] = launch["alg_bytes_per_launch"] / launch["ms"] / 1e6
     out["launch"] = launch
-    out["valu"] = stored_valu(f"{lattice}_{storage}", out["mlups"])
+    out["valu"] = stored_valu(f"{lattice}_{storage}" + ("_fused" if out["schedule"]["fused"] else ""), out["mlups"])
     if check:
         nb, sums = lat.check()
         out["bad_sites"] = nb
