@@ -302,6 +302,35 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
  * device's free memory cannot hold that copy. */
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
 
+/* ---- a step entry point that allocates nothing ---- */
+
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Advances
+ * nrep lattices (1 .. LB_NOALLOC_MAX_REPLICAS; one storage type and one
+ * lattice model) by nsteps >= 0 steps on hip_stream, exactly as
+ * lb_batch_init(reps, nrep, d_pool, hip_stream, LB_INIT_KEEP, t0) followed by
+ * lb_batch_step(nsteps) would (for nrep = 1 the same as lb_init with
+ * LB_INIT_KEEP and lb_step), with no context.  d_pool holds the lattices as
+ * laid out by lb_batch_pool_bytes / lb_batch_offset (one state buffer for
+ * nrep = 1), each in the AA layout of step t0's parity (as the library left
+ * it at step count t0); the caller owns it.  Launch shape: the default
+ * schedule's block size, tilings and XCD remap, the streaming cache policy,
+ * one launch per step over all lattices, no graph.
+ * Memory: calls no allocating routine.  The descriptors, tile prefixes and
+ * the step counter go into one static device array of the library (about
+ * 23 KB, LB_NOALLOC_MAX_REPLICAS descriptors), which each GPU the library
+ * runs on holds until the process ends and which keeps the last call's
+ * contents; every call rewrites what it uses, in stream order, before its
+ * steps.  Calls that overlap on one GPU (on different streams, or from
+ * different threads) race on that array: serialise them.
+ * Errors: nrep above LB_NOALLOC_MAX_REPLICAS returns LB_EUNSUPPORTED;
+ * invalid lattices, pointers, t0 < 0 or nsteps < 0 return LB_EINVAL (nothing
+ * enqueued); launch failures LB_EDEVICE.  Asynchronous: returns once the
+ * work is enqueued. */
+#define LB_NOALLOC_MAX_REPLICAS 64
+int lb_step_noalloc(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_stream, int64_t t0,
+                    int64_t nsteps);
+
 /* ---- calibration ---- */
 
 /* The practical streaming ceiling of the device: copies `bytes` (a positive

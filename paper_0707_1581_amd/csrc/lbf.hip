@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -696,6 +697,65 @@ int gather(lb_ctx* c, int what, float* d_out) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- steps without allocation
+// lb_step_noalloc keeps what a context would hold in device memory (lattice
+// descriptors, tile prefixes, the step counter) in one file-scope device
+// array instead.  Host code never uses the array's name as an address: its
+// device address comes from hipGetSymbolAddress, once per device.
+constexpr size_t NA_OFF_T = 0;                                          // uint64 step counter
+constexpr size_t NA_OFF_BLK = 256;                                      // flat tile prefix
+constexpr size_t NA_OFF_BLKR = NA_OFF_BLK + 4 * (LB_NOALLOC_MAX_REPLICAS + 1 + 63);  // row tile prefix
+constexpr size_t NA_OFF_DESC = (NA_OFF_BLKR + 4 * (LB_NOALLOC_MAX_REPLICAS + 1) + 255) & ~(size_t)255;
+constexpr size_t NA_BYTES = NA_OFF_DESC + sizeof(LatDesc) * LB_NOALLOC_MAX_REPLICAS;
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+constexpr int NA_CHUNK = 8;  // descriptors per setup launch (passed by value: under 4 KB of arguments)
+struct NaDescs {
+  LatDesc d[NA_CHUNK];
+  uint32_t n;
+};
+struct NaMeta {
+  uint32_t blk[LB_NOALLOC_MAX_REPLICAS + 1];
+  uint32_t blk_rows[LB_NOALLOC_MAX_REPLICAS + 1];
+  uint64_t t;
+  uint32_t n;
+};
+static_assert(sizeof(NaDescs) < 4000 && sizeof(NaMeta) < 4000, "setup kernel arguments must stay below 4 KB");
+
+__global__ void __launch_bounds__(64) k_noalloc_descs(NaDescs c, LatDesc* __restrict__ dst) {
+  constexpr uint32_t W = sizeof(LatDesc) / 4;
+  const uint32_t* src = reinterpret_cast<const uint32_t*>(&c.d[0]);
+  uint32_t* out = reinterpret_cast<uint32_t*>(dst);
+  for (uint32_t i = threadIdx.x; i < c.n * W; i += 64) out[i] = src[i];
+}
+
+__global__ void __launch_bounds__(64) k_noalloc_meta(NaMeta m, uint32_t* __restrict__ blk,
+                                                     uint32_t* __restrict__ blk_rows, uint64_t* __restrict__ d_t) {
+  for (uint32_t i = threadIdx.x; i <= m.n; i += 64) {
+    blk[i] = m.blk[i];
+    blk_rows[i] = m.blk_rows[i];
+  }
+  if (threadIdx.x == 0) *d_t = m.t;
+}
+
+// Device address of `scratch` on the current device, looked up once per device.
+int noalloc_scratch(int device, unsigned char** out) {
+  constexpr int MAXDEV = 64;
+  static std::mutex mu;
+  static unsigned char* addr[MAXDEV] = {};
+  if (device < 0 || device >= MAXDEV) return fail(LB_EUNSUPPORTED, "lb_step_noalloc: device index above 63");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(LB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    addr[device] = static_cast<unsigned char*>(p);
+  }
+  *out = addr[device];
+  return LB_OK;
+}
+
 // ================================================================ C ABI
 extern "C" {
 
@@ -1251,6 +1311,100 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
     report[report_len - 1] = 0;
   }
   return rc ? rc : rc2;
+}
+
+int lb_step_noalloc(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_stream, int64_t t0,
+                    int64_t nsteps) {
+  if (!reps || nrep < 1) return fail(LB_EINVAL, "lb_step_noalloc needs at least one lattice");
+  if (nrep > LB_NOALLOC_MAX_REPLICAS)
+    return fail(LB_EUNSUPPORTED, "lb_step_noalloc takes at most LB_NOALLOC_MAX_REPLICAS (64) lattices: its "
+                                 "device scratch holds 64 descriptors; use lb_batch_init / lb_batch_step");
+  for (int r = 0; r < nrep; ++r) {
+    int rc = validate(&reps[r]);
+    if (rc) return rc;
+    if (reps[r].storage != reps[0].storage) return fail(LB_EINVAL, "all lattices need the same storage type");
+    if (reps[r].lattice != reps[0].lattice) return fail(LB_EINVAL, "all lattices need the same lattice model");
+    if (nrep > 1 && is_wide(reps[r])) return fail(LB_EUNSUPPORTED, "batched lattices must hold < 4 GiB per plane");
+  }
+  if (!d_pool || ((uintptr_t)d_pool & 255)) return fail(LB_EINVAL, "d_pool must be non-NULL and 256-byte aligned");
+  if (t0 < 0) return fail(LB_EINVAL, "t0 must be >= 0");
+  if (nsteps < 0) return fail(LB_EINVAL, "nsteps must be >= 0");
+  if (nsteps == 0) return LB_OK;
+
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  unsigned char* base = nullptr;
+  int rc = noalloc_scratch(device, &base);
+  if (rc) return rc;
+  LatDesc* d_lats = reinterpret_cast<LatDesc*>(base + NA_OFF_DESC);
+  uint32_t* d_blk = reinterpret_cast<uint32_t*>(base + NA_OFF_BLK);
+  uint32_t* d_blk_rows = reinterpret_cast<uint32_t*>(base + NA_OFF_BLKR);
+  uint64_t* d_t = reinterpret_cast<uint64_t*>(base + NA_OFF_T);
+  hipStream_t st = (hipStream_t)hip_stream;
+
+  // the library's default launch shape, streaming cache policy, one launch per step
+  constexpr int BLOCK = 256;
+  const int storage = reps[0].storage, lattice = reps[0].lattice;
+  const bool wide = is_wide(reps[0]);
+  int tiling[2] = {1, 0}, remap[2] = {0, 0};
+  if (storage != LB_F32) {
+    tiling[0] = 0;
+    tiling[1] = 1;
+    if (lattice == LB_D3Q19) remap[0] = remap[1] = 8;
+  }
+  if (wide) tiling[0] = tiling[1] = 0;
+
+  // descriptors, in chunks passed by value, then the tile prefixes and the step counter
+  NaMeta meta{};
+  uint64_t off = 0, acc = 0, acc_rows = 0;
+  for (int r0 = 0; r0 < nrep; r0 += NA_CHUNK) {
+    NaDescs chunk{};
+    chunk.n = (uint32_t)std::min(NA_CHUNK, nrep - r0);
+    for (uint32_t k = 0; k < chunk.n; ++k) {
+      const lb_params& p = reps[r0 + k];
+      LatDesc L = make_desc(p, (uint64_t)(uintptr_t)d_pool + off);
+      L.segs = (L.nx + BLOCK - 1) / BLOCK;
+      div_magic(L.segs, L.ds_m, L.ds_s1, L.ds_s2);
+      meta.blk[r0 + k] = (uint32_t)acc;
+      meta.blk_rows[r0 + k] = (uint32_t)acc_rows;
+      acc += (L.nsites + BLOCK - 1) / BLOCK;
+      acc_rows += (uint64_t)L.ny * L.nz * L.segs;
+      off += (lb_state_bytes(&p) + 255) & ~(size_t)255;
+      chunk.d[k] = L;
+    }
+    hipLaunchKernelGGL(k_noalloc_descs, dim3(1), dim3(64), 0, st, chunk, d_lats + r0);
+    HIP_TRY(hipGetLastError());
+  }
+  if (acc >= (1ull << 31) || acc_rows >= (1ull << 31)) return fail(LB_EUNSUPPORTED, "too many workgroups for one launch");
+  meta.blk[nrep] = (uint32_t)acc;
+  meta.blk_rows[nrep] = (uint32_t)acc_rows;
+  meta.t = (uint64_t)t0;
+  meta.n = (uint32_t)nrep;
+  hipLaunchKernelGGL(k_noalloc_meta, dim3(1), dim3(64), 0, st, meta, d_blk, d_blk_rows, d_t);
+  HIP_TRY(hipGetLastError());
+
+  // the steps, in runs of 16 launches between counter advances
+  const uint32_t nlat = (uint32_t)nrep;
+  for (int64_t s0 = 0; s0 < nsteps; s0 += 16) {
+    const int64_t m = std::min<int64_t>(16, nsteps - s0);
+    for (int64_t s = 0; s < m; ++s) {
+      const int parity = (int)((t0 + s0 + s) & 1);
+      const bool rows = tiling[parity] != 0;
+      void* fn = rows ? rows_ptr(lattice, storage, parity, false, BLOCK, false)
+                      : step_ptr(lattice, storage, parity, wide, false, BLOCK, false);
+      const LatDesc* lats = d_lats;
+      const uint32_t* blk = rows ? d_blk_rows : d_blk;
+      uint32_t rm = (uint32_t)remap[parity];
+      const uint64_t* dt = d_t;
+      uint32_t t_off = (uint32_t)s;
+      uint32_t nl = nlat;
+      void* args[] = {&lats, &blk, &nl, &rm, &dt, &t_off};
+      HIP_TRY(hipLaunchKernel(fn, dim3((uint32_t)(rows ? acc_rows : acc)), dim3(BLOCK), args, 0, st));
+    }
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, st, d_t, (uint64_t)m);
+    HIP_TRY(hipGetLastError());
+  }
+  return LB_OK;
 }
 
 }  // extern "C"

@@ -85,7 +85,9 @@ SIGNATURES = [
     ("lb_set_schedule", ctypes.c_int, [_vp, _P(LbSchedule)]),
     ("lb_autotune", ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_char_p, ctypes.c_size_t]),
     ("lb_copy_rate", ctypes.c_int, [_vp, _vp, ctypes.c_size_t, ctypes.c_int32, _vp, _P(ctypes.c_double)]),
+    ("lb_step_noalloc", ctypes.c_int, [_P(LbParams), ctypes.c_int32, _vp, _vp, ctypes.c_int64, ctypes.c_int64]),
 ]
+NOALLOC_MAX_REPLICAS = 64
 
 _lib = None
 
@@ -149,6 +151,22 @@ def copy_rate(gib=4, reps=10, device="cuda", stream=None):
     _check(lib().lb_copy_rate(_aligned(src), _aligned(dst), n, int(reps), sp, ctypes.byref(out)), "lb_copy_rate")
     del src, dst
     return out.value
+
+
+def step_noalloc(replicas, pool, t0, nsteps, storage="f32", lattice="d3q19", stream=None):
+    """lb_step_noalloc: advance the lattices `replicas` (dicts of make_params
+    keywords) whose states lie in the device tensor `pool` (laid out as for
+    an Ensemble; one state for a single lattice) from step t0 by nsteps
+    steps, with no context and no device allocation."""
+    params = [make_params(storage=storage, lattice=lattice, **r) for r in replicas]
+    arr = (LbParams * len(params))(*params)
+    dev = pool.device
+    sp, s = _stream_ptr(dev, stream)
+    _adopt(pool, dev, s)
+    _check(lib().lb_step_noalloc(arr, len(params), _aligned(pool), sp, int(t0), int(nsteps)), "lb_step_noalloc")
+    cur = torch.cuda.current_stream(dev)
+    if s != cur:
+        cur.wait_stream(s)
 
 
 def _stream_ptr(device, stream):

@@ -147,3 +147,23 @@ def test_workloads_generators_are_deterministic():
     assert {r["nx"] for r in a} <= set(workloads.ENSEMBLE_SIZES)
     assert len({r["seed"] for r in a}) == 96
     assert all(1e-5 <= r["kT"] <= 1e-3 and 0 <= r["gamma_shear"] <= 0.9 for r in a)
+
+
+def test_step_noalloc_validates_before_touching_a_device():
+    L = lb.lib()
+    p = lb.make_params(8, 8, 8)
+    arr = (lb.LbParams * 65)(*([p] * 65))
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every check below fails first
+    assert L.lb_step_noalloc(arr, 65, fake, None, 0, 1) == lb.LB_EUNSUPPORTED
+    assert "64" in L.lb_last_error().decode()
+    assert L.lb_step_noalloc(arr, 0, fake, None, 0, 1) == lb.LB_EINVAL
+    assert L.lb_step_noalloc(None, 1, fake, None, 0, 1) == lb.LB_EINVAL
+    assert L.lb_step_noalloc(arr, 1, ctypes.c_void_p((1 << 20) + 4), None, 0, 1) == lb.LB_EINVAL  # misaligned
+    assert L.lb_step_noalloc(arr, 1, None, None, 0, 1) == lb.LB_EINVAL
+    assert L.lb_step_noalloc(arr, 1, fake, None, -1, 1) == lb.LB_EINVAL
+    assert L.lb_step_noalloc(arr, 1, fake, None, 0, -1) == lb.LB_EINVAL
+    mixed = (lb.LbParams * 2)(p, lb.make_params(8, 8, 8, storage="f16"))
+    assert L.lb_step_noalloc(mixed, 2, fake, None, 0, 1) == lb.LB_EINVAL
+    bad = (lb.LbParams * 1)(lb.make_params(0, 8, 8))
+    assert L.lb_step_noalloc(bad, 1, fake, None, 0, 1) == lb.LB_EINVAL
+    assert L.lb_step_noalloc(arr, 1, fake, None, 0, 0) == lb.LB_OK  # nothing to do: no device call
