@@ -208,6 +208,14 @@ def run_lattice(dims, storage, steps, warmup, cfg, check=True, tune=True, lattic
     launch = launch_duration(lat)
     launch["alg_bytes_per_launch"] = alg * launch["site_updates_per_launch_per_site"]
     launch["achieved_gbs"] = launch["alg_bytes_per_launch"] / launch["ms"] / 1e6
+    if lattice == "d3q19" and dims == (512, 512, 512):
+        # HBM bytes per launch counted by the profiler on this machine (mean of the
+        # even and odd launches for AA schedules), if taken on these kernels
+        tr = stored_traffic(storage + ("_fused" if out["schedule"]["fused"] else ""))
+        if tr:
+            launch["traffic"] = tr
+            launch["traffic_over_alg"] = tr / launch["alg_bytes_per_launch"]
+            launch["traffic_gbs"] = tr / launch["ms"] / 1e6
     out["launch"] = launch
     out["valu"] = stored_valu(f"{lattice}_{storage}" + ("_fused" if out["schedule"]["fused"] else ""), out["mlups"])
     if check:
