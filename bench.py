@@ -105,7 +105,7 @@ def progress(msg):
 def launch_duration(lat, reps=10):
     """Mean duration (ms) of one launch of the run's step kernel, from HIP
     events on the lattice's stream around direct (never graph-replayed)
-    calls: under the fused schedule lb_step(4) from even t is two k_step2
+    calls: under the fused schedule lb_step(4) from even t is two fused
     launches, otherwise lb_step(2) is one even and one odd AA launch; each
     call also runs the 1-thread step-counter advance (a few microseconds)."""
     import torch
@@ -122,7 +122,8 @@ def launch_duration(lat, reps=10):
         ev[2 * r + 1].record(lat.stream)
     torch.cuda.synchronize()
     ms = sum(ev[2 * r].elapsed_time(ev[2 * r + 1]) for r in range(reps)) / reps / 2
-    return {"kernel": ("k_step2<fp32/fp16/bf16> (fused pair of steps)" if fused else
+    k2 = "k_step2_2d" if lat.lattice == "d2q9" else "k_step2"
+    return {"kernel": (f"{k2}<fp32/fp16/bf16> (fused pair of steps)" if fused else
                        "k_step / k_step_rows (even and odd AA steps, as scheduled)"),
             "ms": ms, "site_updates_per_launch_per_site": 2 if fused else 1,
             "launches_timed": 2 * reps, "method": f"HIP events around {reps} direct lb_step({n}) calls"}

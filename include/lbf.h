@@ -134,8 +134,8 @@ size_t lb_state_bytes(const lb_params* p);
  * Enqueues the initial state (init_kind) as the state at step count t0
  * (t0 >= 0); d_fields is required for LB_INIT_FIELDS and ignored otherwise.
  * The context stores p by value.  Its default schedule (lb_get_schedule)
- * depends on the state: an fp32 D3Q19 lattice of more than 320 MB with
- * planes below 4 GiB takes the fused two-step schedule when the device has
+ * depends on the state: an fp32 lattice (D3Q19 or D2Q9) of more than 320 MB
+ * with planes below 4 GiB takes the fused two-step schedule when the device has
  * room for its second state buffer, which lb_init then allocates (release
  * it with lb_set_schedule and fused = 0).  With LB_BF16 storage and kT = 0
  * it succeeds and leaves a warning in lb_last_error(). */
@@ -269,11 +269,11 @@ typedef struct {
                         /* the caller's buffer, so between calls it is always  */
                         /* there; steps that do not fill a pair of launches    */
                         /* run as AA steps.  Results are bit-identical to      */
-                        /* fused = 0.  Single D3Q19 lattices with planes below */
-                        /* 4 GiB only (else LB_EUNSUPPORTED, as when the       */
-                        /* second buffer cannot be allocated); the tiling,     */
-                        /* remap and cache-policy fields then apply to those   */
-                        /* AA steps only.                                      */
+                        /* fused = 0.  Single lattices (D3Q19 or D2Q9) with    */
+                        /* planes below 4 GiB only (else LB_EUNSUPPORTED, as   */
+                        /* when the second buffer cannot be allocated); the    */
+                        /* tiling, remap and cache-policy fields then apply to */
+                        /* those AA steps only.                                */
 } lb_schedule;
 
 int lb_get_schedule(const lb_ctx* ctx, lb_schedule* out);
@@ -291,7 +291,7 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
  * interleaved rounds) with each cache policy and, for a batch, replica
  * groups of 0, 64, 128, 160, 192, 224 and 256 MiB, and keeps a variant
  * only if it is at least 1% faster than the first stage's choice; a single
- * D3Q19 lattice also tries the fused two-step schedule there (when the
+ * lattice also tries the fused two-step schedule there (when the
  * device has room for its second buffer).  Applies the best schedule and
  * writes a JSON report (one object per first-stage candidate with its mean
  * even and odd step times, plus refined_even_ms / refined_odd_ms for the

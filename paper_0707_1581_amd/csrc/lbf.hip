@@ -14,6 +14,7 @@
 
 #include "lbf.h"
 #include "lbf_kernels.h"
+#include "lbf_fused2d.h"
 
 using namespace lbf;
 
@@ -198,9 +199,17 @@ void* rows_ptr(int lattice, int storage, int parity, bool res, int block, bool p
                             : rows_ptr_m<D3Q19, false>(storage, parity, res, block);
 }
 
-// Fused two-step passes (D3Q19, planes below 4 GiB): step kernels and their
-// propagation-only twins.
-void* step2_ptr(int storage, bool prop) {
+// Fused two-step passes (D3Q19 and D2Q9, planes below 4 GiB): step kernels
+// and their propagation-only twins.
+void* step2_ptr(int lattice, int storage, bool prop) {
+  if (lattice == LB_D2Q9) {
+    switch (storage) {
+      case LB_F32: return prop ? (void*)&k_step2_2d<ST_F32, true> : (void*)&k_step2_2d<ST_F32, false>;
+      case LB_F16: return prop ? (void*)&k_step2_2d<ST_F16, true> : (void*)&k_step2_2d<ST_F16, false>;
+      case LB_BF16: return prop ? (void*)&k_step2_2d<ST_BF16, true> : (void*)&k_step2_2d<ST_BF16, false>;
+    }
+    return nullptr;
+  }
   switch (storage) {
     case LB_F32: return prop ? (void*)&k_step2<ST_F32, true> : (void*)&k_step2<ST_F32, false>;
     case LB_F16: return prop ? (void*)&k_step2<ST_F16, true> : (void*)&k_step2<ST_F16, false>;
@@ -305,12 +314,15 @@ struct lb_ctx {
   } adv_args;
 
   // fused schedule: the second state buffer (library-owned), the descriptors
-  // of both buffers (d_f2[0] the state, d_f2[1] the second buffer) and the
-  // tile grid of k_step2
+  // of both buffers (d_f2[0] the state, d_f2[1] the second buffer), the tile
+  // grid of k_step2 (D3Q19) or k_step2_2d (D2Q9), the planes (rows) a tile
+  // walks and the workgroup size
   char* d_state_b = nullptr;
   LatDesc* d_f2 = nullptr;
-  uint32_t f2_ntx = 0, f2_nty = 0, f2_ntz = 0;
-  static constexpr uint32_t F2_ZLEN = 32;  // planes per tile column (measured: 32 beats 64 and 128 at 512^3)
+  uint32_t f2_ntx = 0, f2_nty = 0, f2_ntz = 0, f2_len = 0;
+  int f2_threads = 0;
+  static constexpr uint32_t F2_ZLEN = 32;   // planes per tile column (measured: 32 beats 64 and 128 at 512^3)
+  static constexpr uint32_t F2D_YLEN = 32;  // rows per D2Q9 segment column (16384^2: 24-32 beat 16, 64 and 128)
   struct F2Args {
     const LatDesc* src;
     uint64_t dst;
@@ -383,9 +395,19 @@ int upload_schedule(lb_ctx* c) {
     LatDesc f2[2] = {c->lats[0], c->lats[0]};
     f2[1].base = (uint64_t)(uintptr_t)c->d_state_b;
     HIP_TRY(hipMemcpy(c->d_f2, f2, sizeof(f2), hipMemcpyHostToDevice));
-    c->f2_ntx = (f2[0].nx + 63u) / 64u;
-    c->f2_nty = (f2[0].ny + (uint32_t)F2_TY - 1u) / (uint32_t)F2_TY;
-    c->f2_ntz = (f2[0].nz + lb_ctx::F2_ZLEN - 1u) / lb_ctx::F2_ZLEN;
+    if (c->lattice == LB_D2Q9) {
+      c->f2_ntx = (f2[0].nx + (uint32_t)F2D_W - 1u) / (uint32_t)F2D_W;
+      c->f2_nty = (f2[0].ny + lb_ctx::F2D_YLEN - 1u) / lb_ctx::F2D_YLEN;
+      c->f2_ntz = 1;
+      c->f2_len = lb_ctx::F2D_YLEN;
+      c->f2_threads = F2D_THREADS;
+    } else {
+      c->f2_ntx = (f2[0].nx + 63u) / 64u;
+      c->f2_nty = (f2[0].ny + (uint32_t)F2_TY - 1u) / (uint32_t)F2_TY;
+      c->f2_ntz = (f2[0].nz + lb_ctx::F2_ZLEN - 1u) / lb_ctx::F2_ZLEN;
+      c->f2_len = lb_ctx::F2_ZLEN;
+      c->f2_threads = F2_THREADS;
+    }
   }
   drop_graph(c);
   return LB_OK;
@@ -393,7 +415,9 @@ int upload_schedule(lb_ctx* c) {
 
 // The fused schedule's second buffer: allocated once, the size of the state,
 // if the device has room for it beside a margin of 1 GiB.
-bool fused_eligible(const lb_ctx* c) { return c->lattice == LB_D3Q19 && c->reps.size() == 1 && !c->wide; }
+bool fused_eligible(const lb_ctx* c) {
+  return (c->lattice == LB_D3Q19 || c->lattice == LB_D2Q9) && c->reps.size() == 1 && !c->wide;
+}
 
 int ensure_state_b(lb_ctx* c) {
   if (c->d_state_b) return LB_OK;
@@ -457,14 +481,14 @@ int launch_step(lb_ctx* c, uint32_t t_off, int parity, bool prop = false) {
 lb_ctx::F2Args pass_args(const lb_ctx* c, uint32_t t_off, bool to_b) {
   return {to_b ? c->d_f2 : c->d_f2 + 1,
           to_b ? (uint64_t)(uintptr_t)c->d_state_b : c->lats[0].base,
-          c->d_t, t_off, c->f2_ntx, c->f2_nty, lb_ctx::F2_ZLEN};
+          c->d_t, t_off, c->f2_ntx, c->f2_nty, c->f2_len};
 }
 
 int launch_pass(lb_ctx* c, uint32_t t_off, bool to_b, bool prop = false) {
   lb_ctx::F2Args a = pass_args(c, t_off, to_b);
   void* args[] = {&a.src, &a.dst, &a.d_t, &a.t_off, &a.ntx, &a.nty, &a.zlen};
-  HIP_TRY(hipLaunchKernel(step2_ptr(c->storage, prop), dim3(c->f2_ntx * c->f2_nty * c->f2_ntz), dim3(F2_THREADS),
-                          args, 0, c->stream));
+  HIP_TRY(hipLaunchKernel(step2_ptr(c->lattice, c->storage, prop), dim3(c->f2_ntx * c->f2_nty * c->f2_ntz),
+                          dim3(c->f2_threads), args, 0, c->stream));
   return LB_OK;
 }
 
@@ -504,7 +528,8 @@ int build_graph(lb_ctx* c) {
     c->graph_f2_args[p] = pass_args(c, (uint32_t)(2 * p), (p & 1) == 0);
     lb_ctx::F2Args& a = c->graph_f2_args[p];
     void* args[] = {&a.src, &a.dst, &a.d_t, &a.t_off, &a.ntx, &a.nty, &a.zlen};
-    int rc = add_node(step2_ptr(c->storage, false), c->f2_ntx * c->f2_nty * c->f2_ntz, F2_THREADS, args);
+    int rc = add_node(step2_ptr(c->lattice, c->storage, false), c->f2_ntx * c->f2_nty * c->f2_ntz, c->f2_threads,
+                      args);
     if (rc) return rc;
   }
   const int K1 = K - 4 * units;  // AA steps per group, from step 4 * units of the chunk
@@ -657,11 +682,12 @@ int default_schedule(lb_ctx* c) {
       c->sched.resident = 1;
       c->sched.group_mb = 224;
     }
-    // fp32 D3Q19 state beyond the cache streams through HBM: two fused steps
-    // per launch move about half the bytes (512^3: 5.2-5.4 against 7.2 ms
-    // per two steps), when the second buffer fits on the device.  The 16-bit
-    // forms keep one step per launch: their collision already keeps the VALU
-    // busy enough that the fused pass, with its halo collisions, is slower.
+    // fp32 state beyond the cache streams through HBM: two fused steps per
+    // launch move about half the bytes (512^3 D3Q19: 5.2-5.4 against 7.2 ms
+    // per two steps; 16384^2 D2Q9: 4.35 against 6.84 ms), when the second
+    // buffer fits on the device.  The 16-bit forms keep one step per launch:
+    // their collision already keeps the VALU busy enough that the fused pass
+    // is slower.
     if (c->storage == LB_F32 && fused_eligible(c) && total > 320 * MB) {
       const std::string keep = g_last_error;
       if (ensure_state_b(c) == LB_OK) c->sched.fused = 1;
@@ -1070,7 +1096,7 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s) {
   if (s->group_mb < 0 || s->group_mb > (1 << 20)) return fail(LB_EINVAL, "group_mb must be in [0, 2^20]");
   if (s->fused != 0 && s->fused != 1) return fail(LB_EINVAL, "fused must be 0 or 1");
   if (s->fused && !fused_eligible(ctx))
-    return fail(LB_EUNSUPPORTED, "the fused schedule needs a single D3Q19 lattice with planes below 4 GiB");
+    return fail(LB_EUNSUPPORTED, "the fused schedule needs a single lattice with planes below 4 GiB");
 
   HIP_TRY(hipSetDevice(ctx->device));
   if (s->fused) {

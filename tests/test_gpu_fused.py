@@ -1,6 +1,7 @@
 """The fused two-step schedule: each launch applies Eq. LBE twice (collision
-with noise, push) to a whole D3Q19 lattice, reading the state once and writing
-it once into a second buffer, and a second launch brings the state back.
+with noise, push) to a whole D3Q19 or D2Q9 lattice, reading the state once and
+writing it once into a second buffer, and a second launch brings the state
+back.
 
 Pinned three ways:
   - bit for bit against the single-step (AA) schedule on boxes that exercise
@@ -191,12 +192,12 @@ def test_fused_schedule_rules():
         lat = lbf.Lattice(nx=dims[0], ny=dims[1], nz=dims[2], **base, storage=st, init="rest")
         assert lat.schedule()["fused"] == want, (dims, st, lat.schedule())
         lat.close()
-    # D2Q9 and ensembles have no fused pass
-    lat = lbf.Lattice(nx=64, ny=48, nz=1, **base, init="rest", lattice="d2q9")
-    with pytest.raises(lb.LBError) as ei:
-        lat.set_schedule(fused=1)
-    assert ei.value.code == lb.LB_EUNSUPPORTED
-    lat.close()
+    # D2Q9 likewise (4096^2 fp32: 604 MB; 2048^2: 151 MB, resident)
+    for dims, st, want in [((4096, 4096), "f32", 1), ((2048, 2048), "f32", 0), ((4096, 4096), "bf16", 0)]:
+        lat = lbf.Lattice(nx=dims[0], ny=dims[1], nz=1, **base, storage=st, init="rest", lattice="d2q9")
+        assert lat.schedule()["fused"] == want, (dims, st, lat.schedule())
+        lat.close()
+    # ensembles have no fused pass
     ens = lbf.Ensemble([dict(base, nx=16, ny=16, nz=16, seed=s) for s in range(2)], init="rest")
     with pytest.raises(lb.LBError) as ei:
         ens.set_schedule(fused=1)
@@ -238,5 +239,159 @@ def test_autotune_tries_the_fused_schedule():
     lat.step(20)
     ref.step(20)
     assert torch.equal(lat.state, ref.state)
+    lat.close()
+    ref.close()
+
+
+# ---------------------------------------------------------------- D2Q9
+BOXES_2D = [(1, 1), (2, 2), (5, 3), (256, 32), (257, 33), (1000, 130), (64, 200), (1030, 7), (3, 131)]
+
+
+def _cfg2(dims, seed=4321):
+    nx, ny = dims
+    return dict(nx=nx, ny=ny, nz=1, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=-0.3,
+                gamma_even=0.2, seed=seed, lattice="d2q9")
+
+
+@pytest.mark.parametrize("dims", BOXES_2D)
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_fused_2d_equals_single_steps(dims, storage):
+    """Segments that clip at the box edge, segments wider than the box, rows
+    chunks shorter than a chunk, boxes of one row or column."""
+    cfg = _cfg2(dims)
+    a = lbf.Lattice(**cfg, storage=storage, init="thermal")
+    b = lbf.Lattice(**cfg, storage=storage, init="thermal")
+    a.set_schedule(block=256, xcd_remap=0, graph_chunk=16, tiling=0, fused=0)
+    b.set_schedule(block=256, xcd_remap=0, graph_chunk=16, tiling=0, fused=1)
+    assert b.schedule()["fused"] == 1
+    for n in (1, 3, 4, 7, 16, 21, 37):
+        a.step(n)
+        b.step(n)
+        assert a.t == b.t
+        assert torch.equal(a.state, b.state), (dims, storage, a.t)
+    assert b.check()[0] == 0
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("chunk", [2, 6, 30])
+def test_fused_2d_graph_chunks(chunk):
+    cfg = _cfg2((1000, 130), seed=77)
+    a = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    b = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    a.set_schedule(block=128, xcd_remap=1, graph_chunk=chunk, tiling=1, fused=0)
+    b.set_schedule(block=128, xcd_remap=1, graph_chunk=chunk, tiling=1, fused=1)
+    for n in (2 * chunk + 1, chunk, 3):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.state, b.state), (chunk, a.t)
+    a.close()
+    b.close()
+
+
+def test_fused_2d_trajectory_matches_oracle():
+    """The D2Q9 parity workload (64 x 48, rest start, kT = 1e-4, 100 steps)
+    under the fused schedule matches the FP64 oracle to 1e-5."""
+    cfg = dict(workloads.SMALL_2D)
+    lat = lbf.Lattice(**cfg, storage="f32", init="rest")
+    lat.set_schedule(block=256, xcd_remap=0, graph_chunk=16, tiling=0, fused=1)
+    p = oracle_params(cfg)
+    n = oracle.init(p, oracle.INIT_REST)
+    t = 0
+    for target in (4, 8, 99, 100):
+        lat.step(target - t)
+        n = oracle.run(p, n, t, target - t)
+        t = target
+        err = scaled_err(gpu_pops(lat), n, cfg["rho0"])
+        say(f"fused d2q9 64x48 t={t}: max scaled err {err:.2e}")
+        assert err < 1e-5, (t, err)
+    lat.close()
+
+
+def test_fused_2d_propagation_is_exact_shift():
+    cfg = _cfg2((1000, 130), seed=5)
+    lat = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    lat.set_schedule(block=256, xcd_remap=0, graph_chunk=16, tiling=0, fused=1)
+    c = oracle.tables(oracle.D2Q9)[0]
+    before = lat.populations().clone()
+    for n in (4, 5, 8):
+        lat.propagate(n)
+        after = lat.populations()
+        k = lat.t
+        for i in range(9):
+            want = torch.roll(before[i], shifts=(k * int(c[i, 1]), k * int(c[i, 0])), dims=(1, 2))
+            assert torch.equal(after[i], want), (n, i)
+    lat.close()
+
+
+def _patch_oracle_2d(p, nx, ny, center, before, t0, nsteps):
+    """The 2D form of _patch_oracle: evolve the (2 nsteps + 1)^2
+    neighbourhood of `center` (populations `before`, (9, W, W)) with the
+    oracle's single-site update and push streaming; returns the center's
+    populations afterwards."""
+    c = oracle.tables(oracle.D2Q9)[0]
+    W = 2 * nsteps + 1
+    cur = before
+    for s in range(nsteps):
+        new = np.zeros_like(cur)
+        lo, hi = s, W - s
+        for y in range(lo, hi):
+            for x in range(lo, hi):
+                gx = (center[0] - nsteps + x) % nx
+                gy = (center[1] - nsteps + y) % ny
+                post = oracle.collide_site(p, cur[:, y, x], gx + nx * gy, t0 + s)
+                for i in range(9):
+                    yy, xx = y + c[i, 1], x + c[i, 0]
+                    if 0 <= yy < W and 0 <= xx < W:
+                        new[i, yy, xx] = post[i]
+        cur = new
+    return cur[:, nsteps, nsteps]
+
+
+def test_16384_fused_2d_sampled_parity():
+    """The D2Q9 throughput box under its default (fused) schedule: one pair
+    of passes from t = 0 and one AA step plus a pair from an odd t, checked
+    at sampled sites (faces, corners and segment and chunk seams included)
+    against the oracle's evolution of each site's neighbourhood, and the
+    whole state bit for bit against the AA schedule."""
+    cfg = dict(workloads.LARGE_2D)
+    L = cfg["nx"]
+    lat = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    assert lat.schedule()["fused"] == 1, lat.schedule()
+    rng = np.random.default_rng(23)
+    pts = np.vstack([rng.integers(0, L, size=(40, 2)),
+                     [[0, 0], [L - 1, L - 1], [0, L - 1], [L - 1, 0], [255, 31], [256, 32], [511, 63]]])
+    p = oracle_params(cfg)
+    for t_start, R in ((0, 4), (19, 5)):
+        if lat.t < t_start:
+            lat.step(t_start - lat.t)
+        off = np.arange(-R, R + 1)
+        pops = lat.populations()
+        patches = []
+        for x, y in pts:
+            iy = torch.as_tensor((y + off) % L, device=pops.device)[:, None]
+            ix = torch.as_tensor((x + off) % L, device=pops.device)[None, :]
+            patches.append(pops[:, 0, iy, ix].double().cpu().numpy())
+        del pops
+        torch.cuda.empty_cache()
+        t0 = lat.t
+        lat.step(R)
+        pops = lat.populations()
+        idx = torch.as_tensor(pts, device=pops.device)
+        got = pops[:, 0, idx[:, 1], idx[:, 0]].double().cpu().numpy()
+        del pops
+        torch.cuda.empty_cache()
+        a = oracle.tables(oracle.D2Q9)[1]
+        worst = 0.0
+        for k, center in enumerate(pts):
+            want = _patch_oracle_2d(p, L, L, center, patches[k], t0, R)
+            worst = max(worst, float((np.abs(got[:, k] - want) / (a * cfg["rho0"])).max()))
+        say(f"16384^2 d2q9 fused, t={t0} -> {t0 + R}: {len(pts)} sites, max scaled err {worst:.2e}")
+        assert worst < 1e-5, worst
+    ref = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    ref.set_schedule(block=256, xcd_remap=0, graph_chunk=16, tiling=(1, 0), fused=0)
+    ref.step(lat.t)
+    assert torch.equal(lat.state, ref.state)
+    assert lat.check()[0] == 0
     lat.close()
     ref.close()
