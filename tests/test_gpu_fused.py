@@ -53,6 +53,39 @@ def test_fused_equals_single_steps(dims, storage):
     b.close()
 
 
+@pytest.mark.parametrize("lattice,dims", [("d3q19", (70, 13, 9)), ("d2q9", (1000, 130, 1))])
+@pytest.mark.parametrize("variant", [dict(kT=0.0, gamma_bulk=-0.4, gamma_shear=0.9),
+                                     dict(thermal_modes="stress_only", gamma_odd=0.0, gamma_even=0.0),
+                                     dict(gamma_bulk=1.0, gamma_shear=-1.0, gamma_odd=1.0, gamma_even=-1.0),
+                                     dict(seed=2 ** 40 + 3)])
+def test_fused_collision_branches(lattice, dims, variant):
+    """The other branches of the collision under the fused pass: no noise
+    (kT = 0), the stress-only model, rates of +-1 in every class, a 64-bit
+    seed; from a large step count, so the counter's high word is set."""
+    nx, ny, nz = dims
+    cfg = dict(nx=nx, ny=ny, nz=nz, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=-0.3,
+               gamma_even=0.2, seed=99, lattice=lattice)
+    cfg.update(variant)
+    t0 = 2 ** 32 - 6
+    a = lbf.Lattice(**cfg, storage="f32", init="thermal" if cfg["kT"] > 0 else "rest", t0=t0)
+    b = lbf.Lattice(**cfg, storage="f32", init="thermal" if cfg["kT"] > 0 else "rest", t0=t0)
+    if cfg["kT"] == 0:  # a deterministic start away from rest: a few noisy steps of a twin
+        w = lbf.Lattice(**dict(cfg, kT=1e-4), storage="f32", init="thermal", t0=t0)
+        w.step(2)
+        a.state.copy_(w.state)
+        b.state.copy_(w.state)
+        w.close()
+    a.set_schedule(block=256, xcd_remap=0, graph_chunk=16, tiling=0, fused=0)
+    b.set_schedule(block=256, xcd_remap=0, graph_chunk=16, tiling=0, fused=1)
+    for n in (4, 9, 16):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.state, b.state), (lattice, variant, a.t)
+    assert a.t > 2 ** 32
+    a.close()
+    b.close()
+
+
 @pytest.mark.parametrize("chunk", [2, 4, 6, 8, 30])
 def test_fused_graph_chunks(chunk):
     """Chunks that are not a multiple of four run their last two steps as AA
