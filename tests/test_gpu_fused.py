@@ -166,13 +166,14 @@ def _patch_oracle(p, L, center, before, t0, nsteps):
     return cur[:, nsteps, nsteps, nsteps]
 
 
-def test_512_fused_sampled_parity():
-    """The benchmark box under its default (fused) schedule: one pair of
-    passes from t = 0, and one AA step plus one pair from an odd t, checked
-    at sampled sites
-    (faces and edges included) against the oracle's evolution of each site's
-    neighbourhood, and the whole state bit for bit against the AA schedule."""
-    cfg = dict(workloads.LARGE)
+@pytest.mark.parametrize("box", ["LARGE", "XLARGE"])
+def test_fused_sampled_parity_full_size(box):
+    """The benchmark's fp32 boxes (512^3 and 768^3) under their default
+    (fused) schedule: one pair of passes from t = 0, and one AA step plus one
+    pair from an odd t, checked at sampled sites (faces, edges and tile seams
+    included) against the oracle's evolution of each site's neighbourhood,
+    and the whole state bit for bit against the AA schedule."""
+    cfg = dict(getattr(workloads, box))
     L = cfg["nx"]
     lat = lbf.Lattice(**cfg, storage="f32", init="thermal")
     assert lat.schedule()["fused"] == 1, lat.schedule()
@@ -206,7 +207,7 @@ def test_512_fused_sampled_parity():
         for k, center in enumerate(pts):
             want = _patch_oracle(p, L, center, patches[k], t0, R)
             worst = max(worst, float((np.abs(got[:, k] - want) / (a * cfg["rho0"])).max()))
-        say(f"512^3 fused, t={t0} -> {t0 + R}: {len(pts)} sites, max scaled err {worst:.2e}")
+        say(f"{L}^3 fused, t={t0} -> {t0 + R}: {len(pts)} sites, max scaled err {worst:.2e}")
         assert worst < 1e-5, worst
     # the whole state against the single-step schedule from the same start
     ref = lbf.Lattice(**cfg, storage="f32", init="thermal")
@@ -216,6 +217,8 @@ def test_512_fused_sampled_parity():
     assert lat.check()[0] == 0
     lat.close()
     ref.close()
+    del lat, ref
+    torch.cuda.empty_cache()
 
 
 def test_fused_schedule_rules():
