@@ -67,6 +67,7 @@ k_step2_2d(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* _
   using M = D2Q9;
   using C = Codec<S>;
   using T = typename C::T;
+  using U = typename Carry<T>::U;  // register form of the prefetched values
   using R = F2DRing;
   constexpr int Q = M::Q;
   constexpr uint32_t ES = sizeof(T);
@@ -110,23 +111,23 @@ k_step2_2d(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* _
     const int yy = (int)y0 + (int)it - 1;
     return yy < 0 ? ny - 1u : ((uint32_t)yy >= ny ? 0u : (uint32_t)yy);
   };
-  auto load_row = [&](uint32_t it, T (&v)[Q]) {
+  auto load_row = [&](uint32_t it, U (&v)[Q]) {
     const uint32_t so = yfirst(it) * nx * ES;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) v[i] = Raw<T>::template ld<0>(plane_rsrc(L, i, ES), x1 * ES, so);
+    for (int i = 0; i < Q; ++i) v[i] = Carry<T>::wrap(Raw<T>::template ld<0>(plane_rsrc(L, i, ES), x1 * ES, so));
   };
   // first step of row u = it - 1: collide, push into P(u - 1), P(u), P(u + 1)
-  auto first = [&](uint32_t it, const T (&v)[Q]) {
+  auto first = [&](uint32_t it, const U (&v)[Q]) {
     if (!act1 || it > YC + 1u) return;
     float d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = C::dec(v[i]);
+    for (int i = 0; i < Q; ++i) d[i] = C::dec(Carry<T>::unwrap(v[i]));
     if constexpr (!PROP) collide<M>(L, d, x1 + yfirst(it) * nx, (uint32_t)t, (uint32_t)(t >> 32));
     const uint32_t fs = (it + 2u) % 3u, us = it % 4u, ds = it & 1u;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int tx = sx + M::CX[i];
-      if (tx >= 0 && tx < (int)TW) ring[R::base(i, fs, us, ds) + (uint32_t)tx] = PROP ? v[i] : C::enc(d[i]);
+      if (tx >= 0 && tx < (int)TW) ring[R::base(i, fs, us, ds) + (uint32_t)tx] = PROP ? Carry<T>::unwrap(v[i]) : C::enc(d[i]);
     }
   };
   // second step of row y0 + it - 3 from P(it - 3), pushed into the destination
@@ -161,7 +162,7 @@ k_step2_2d(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* _
   // two rows of loads in flight (register sets a and c, unrolled by two);
   // the first and second steps of a phase touch different ring slots, so one
   // barrier per phase suffices
-  T a[Q], c[Q];
+  U a[Q], c[Q];
   if (act1) {
     load_row(0u, a);
     load_row(1u, c);

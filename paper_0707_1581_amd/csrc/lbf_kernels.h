@@ -221,6 +221,26 @@ template <> struct Raw<uint16_t> {
   }
 };
 
+// Register form of a loaded value that is carried across loop iterations (the
+// fused passes' prefetched planes).  16-bit values travel zero-extended in a
+// 32-bit register each: an array of 16-bit values is otherwise kept as packed
+// pairs, and packing a pair waits for both loads right after they are issued.
+template <class T> struct Carry {
+  using U = T;
+  static __device__ __forceinline__ U wrap(T v) { return v; }
+  static __device__ __forceinline__ T unwrap(U u) { return u; }
+};
+template <> struct Carry<_Float16> {
+  using U = uint32_t;
+  static __device__ __forceinline__ U wrap(_Float16 v) { return (uint32_t)__builtin_bit_cast(uint16_t, v); }
+  static __device__ __forceinline__ _Float16 unwrap(U u) { return __builtin_bit_cast(_Float16, (uint16_t)u); }
+};
+template <> struct Carry<uint16_t> {
+  using U = uint32_t;
+  static __device__ __forceinline__ U wrap(uint16_t v) { return (uint32_t)v; }
+  static __device__ __forceinline__ uint16_t unwrap(U u) { return (uint16_t)u; }
+};
+
 template <class T, int POL, class Off>
 __device__ __forceinline__ T ld(const LatDesc& L, int plane, Off o) {
   if constexpr (sizeof(Off) == 4) {
@@ -750,6 +770,7 @@ k_step2(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* __re
   using M = D3Q19;
   using C = Codec<S>;
   using T = typename C::T;
+  using U = typename Carry<T>::U;  // register form of the prefetched values
   using R = F2Ring;
   constexpr int Q = M::Q;
   constexpr uint32_t ES = sizeof(T);
@@ -802,24 +823,24 @@ k_step2(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* __re
     const int zz = (int)z0 + (int)it - 1;
     return zz < 0 ? nz - 1u : ((uint32_t)zz >= nz ? 0u : (uint32_t)zz);
   };
-  auto load_plane = [&](uint32_t it, T (&v)[Q]) {
+  auto load_plane = [&](uint32_t it, U (&v)[Q]) {
     const uint32_t so = zfirst(it) * nxy * ES;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) v[i] = Raw<T>::template ld<0>(plane_rsrc(L, i, ES), sxy * ES, so);
+    for (int i = 0; i < Q; ++i) v[i] = Carry<T>::wrap(Raw<T>::template ld<0>(plane_rsrc(L, i, ES), sxy * ES, so));
   };
   // first step of plane u = it - 1: collide, push into P(u - 1), P(u), P(u + 1)
-  auto first = [&](uint32_t it, const T (&v)[Q]) {
+  auto first = [&](uint32_t it, const U (&v)[Q]) {
     if (!act1 || it > ZC + 1u) return;
     float d[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = C::dec(v[i]);
+    for (int i = 0; i < Q; ++i) d[i] = C::dec(Carry<T>::unwrap(v[i]));
     if constexpr (!PROP) collide<M>(L, d, sxy + zfirst(it) * nxy, (uint32_t)t, (uint32_t)(t >> 32));
     const uint32_t fs = (it + 2u) % 3u, us = it % 4u, ds = it & 1u;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int tx = sx + M::CX[i], ty = sy + M::CY[i];
       if (tx >= 0 && tx < (int)TW && ty >= 0 && ty < (int)TH)
-        ring[R::base(i, fs, us, ds) + (uint32_t)(s1idx + M::CY[i] * 64 + M::CX[i])] = PROP ? v[i] : C::enc(d[i]);
+        ring[R::base(i, fs, us, ds) + (uint32_t)(s1idx + M::CY[i] * 64 + M::CX[i])] = PROP ? Carry<T>::unwrap(v[i]) : C::enc(d[i]);
     }
   };
   // second step of plane z0 + it - 3 from P(it - 3), pushed into the destination
@@ -855,7 +876,7 @@ k_step2(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* __re
   // two planes of loads in flight (register sets a and c, unrolled by two so
   // that both stay in registers); the first and second steps of a phase touch
   // different ring slots, so one barrier per phase suffices
-  T a[Q], c[Q];
+  U a[Q], c[Q];
   if (act1) {
     load_plane(0u, a);
     load_plane(1u, c);
