@@ -135,8 +135,9 @@ size_t lb_state_bytes(const lb_params* p);
  * (t0 >= 0); d_fields is required for LB_INIT_FIELDS and ignored otherwise.
  * The context stores p by value.  Its default schedule (lb_get_schedule)
  * depends on the state: an fp32 lattice (D3Q19 or D2Q9) of more than 320 MB
- * with planes below 4 GiB takes the fused two-step schedule when the device has
- * room for its second state buffer, which lb_init then allocates (release
+ * takes the fused two-step schedule when the device has room for its second
+ * state buffer (and its z-planes, or D2Q9 rows, hold less than 4 GiB per
+ * population), which lb_init then allocates (release
  * it with lb_set_schedule and fused = 0).  With LB_BF16 storage and kT = 0
  * it succeeds and leaves a warning in lb_last_error(). */
 int lb_init(const lb_params* p, void* d_state, void* hip_stream, int32_t init_kind,
@@ -269,9 +270,10 @@ typedef struct {
                         /* the caller's buffer, so between calls it is always  */
                         /* there; steps that do not fill a pair of launches    */
                         /* run as AA steps.  Results are bit-identical to      */
-                        /* fused = 0.  Single lattices (D3Q19 or D2Q9) with    */
-                        /* planes below 4 GiB only (else LB_EUNSUPPORTED, as   */
-                        /* when the second buffer cannot be allocated); the    */
+                        /* fused = 0.  Single lattices (D3Q19 or D2Q9) whose   */
+                        /* z-planes (D2Q9: rows) hold less than 4 GiB per      */
+                        /* population only (else LB_EUNSUPPORTED, as when the  */
+                        /* second buffer cannot be allocated); the             */
                         /* tiling, remap and cache-policy fields then apply to */
                         /* those AA steps only.                                */
 } lb_schedule;

@@ -199,23 +199,25 @@ void* rows_ptr(int lattice, int storage, int parity, bool res, int block, bool p
                             : rows_ptr_m<D3Q19, false>(storage, parity, res, block);
 }
 
-// Fused two-step passes (D3Q19 and D2Q9, planes below 4 GiB): step kernels
-// and their propagation-only twins.
-void* step2_ptr(int lattice, int storage, bool prop) {
-  if (lattice == LB_D2Q9) {
-    switch (storage) {
-      case LB_F32: return prop ? (void*)&k_step2_2d<ST_F32, true> : (void*)&k_step2_2d<ST_F32, false>;
-      case LB_F16: return prop ? (void*)&k_step2_2d<ST_F16, true> : (void*)&k_step2_2d<ST_F16, false>;
-      case LB_BF16: return prop ? (void*)&k_step2_2d<ST_BF16, true> : (void*)&k_step2_2d<ST_BF16, false>;
-    }
-    return nullptr;
-  }
+// Fused two-step passes (D3Q19 and D2Q9): step kernels and their
+// propagation-only twins; wide: planes of 4 GiB or more, addressed one
+// z-plane (row) at a time.
+template <int S, bool W>
+void* step2_ptr_s(int lattice, bool prop) {
+  if (lattice == LB_D2Q9) return prop ? (void*)&k_step2_2d<S, true, W> : (void*)&k_step2_2d<S, false, W>;
+  return prop ? (void*)&k_step2<S, true, W> : (void*)&k_step2<S, false, W>;
+}
+template <bool W>
+void* step2_ptr_w(int lattice, int storage, bool prop) {
   switch (storage) {
-    case LB_F32: return prop ? (void*)&k_step2<ST_F32, true> : (void*)&k_step2<ST_F32, false>;
-    case LB_F16: return prop ? (void*)&k_step2<ST_F16, true> : (void*)&k_step2<ST_F16, false>;
-    case LB_BF16: return prop ? (void*)&k_step2<ST_BF16, true> : (void*)&k_step2<ST_BF16, false>;
+    case LB_F32: return step2_ptr_s<ST_F32, W>(lattice, prop);
+    case LB_F16: return step2_ptr_s<ST_F16, W>(lattice, prop);
+    case LB_BF16: return step2_ptr_s<ST_BF16, W>(lattice, prop);
   }
   return nullptr;
+}
+void* step2_ptr(int lattice, int storage, bool wide, bool prop) {
+  return wide ? step2_ptr_w<true>(lattice, storage, prop) : step2_ptr_w<false>(lattice, storage, prop);
 }
 
 // Initial states (rest, thermal, fields), gathers (populations, moments,
@@ -413,11 +415,18 @@ int upload_schedule(lb_ctx* c) {
   return LB_OK;
 }
 
+// The fused passes take one lattice and address its planes one z-plane
+// (D3Q19) or one row (D2Q9) at a time, so a plane may exceed 4 GiB but such
+// a slice may not.
+bool fused_eligible(const lb_ctx* c) {
+  if (c->reps.size() != 1 || (c->lattice != LB_D3Q19 && c->lattice != LB_D2Q9)) return false;
+  const lb_params& p = c->reps[0];
+  const uint64_t slice = (uint64_t)p.nx * (c->lattice == LB_D2Q9 ? 1u : (uint64_t)p.ny) * elem_size(c->storage);
+  return slice < (1ull << 32);
+}
+
 // The fused schedule's second buffer: allocated once, the size of the state,
 // if the device has room for it beside a margin of 1 GiB.
-bool fused_eligible(const lb_ctx* c) {
-  return (c->lattice == LB_D3Q19 || c->lattice == LB_D2Q9) && c->reps.size() == 1 && !c->wide;
-}
 
 int ensure_state_b(lb_ctx* c) {
   if (c->d_state_b) return LB_OK;
@@ -487,7 +496,7 @@ lb_ctx::F2Args pass_args(const lb_ctx* c, uint32_t t_off, bool to_b) {
 int launch_pass(lb_ctx* c, uint32_t t_off, bool to_b, bool prop = false) {
   lb_ctx::F2Args a = pass_args(c, t_off, to_b);
   void* args[] = {&a.src, &a.dst, &a.d_t, &a.t_off, &a.ntx, &a.nty, &a.zlen};
-  HIP_TRY(hipLaunchKernel(step2_ptr(c->lattice, c->storage, prop), dim3(c->f2_ntx * c->f2_nty * c->f2_ntz),
+  HIP_TRY(hipLaunchKernel(step2_ptr(c->lattice, c->storage, c->wide, prop), dim3(c->f2_ntx * c->f2_nty * c->f2_ntz),
                           dim3(c->f2_threads), args, 0, c->stream));
   return LB_OK;
 }
@@ -528,7 +537,7 @@ int build_graph(lb_ctx* c) {
     c->graph_f2_args[p] = pass_args(c, (uint32_t)(2 * p), (p & 1) == 0);
     lb_ctx::F2Args& a = c->graph_f2_args[p];
     void* args[] = {&a.src, &a.dst, &a.d_t, &a.t_off, &a.ntx, &a.nty, &a.zlen};
-    int rc = add_node(step2_ptr(c->lattice, c->storage, false), c->f2_ntx * c->f2_nty * c->f2_ntz, c->f2_threads,
+    int rc = add_node(step2_ptr(c->lattice, c->storage, c->wide, false), c->f2_ntx * c->f2_nty * c->f2_ntz, c->f2_threads,
                       args);
     if (rc) return rc;
   }
@@ -668,31 +677,31 @@ int default_schedule(lb_ctx* c) {
   else if (c->lattice == LB_D2Q9) c->sched = lb_schedule{256, 0, 16, {0, 0}, {0, 1}, 0, 0, 0};
   else c->sched = lb_schedule{256, 0, 16, {8, 8}, {0, 1}, 0, 0, 0};
   if (c->wide) c->sched.tiling[0] = c->sched.tiling[1] = 0;
+  uint64_t total = 0, largest = 0;
+  for (const lb_params& p : c->reps) {
+    const uint64_t b = (uint64_t)q_of(p.lattice) * sites_of(p) * elem_size(p.storage);
+    total += b;
+    largest = std::max(largest, b);
+  }
+  constexpr uint64_t MB = 1000000, MIB = 1ull << 20;
   if (!c->wide) {
-    uint64_t total = 0, largest = 0;
-    for (const lb_params& p : c->reps) {
-      const uint64_t b = (uint64_t)q_of(p.lattice) * sites_of(p) * elem_size(p.storage);
-      total += b;
-      largest = std::max(largest, b);
-    }
-    constexpr uint64_t MB = 1000000, MIB = 1ull << 20;
     if (c->reps.size() == 1) {
       if (total >= 32 * MB && total <= 320 * MB) c->sched.resident = 1;
     } else if (total >= 32 * MB && largest <= 224 * MIB) {
       c->sched.resident = 1;
       c->sched.group_mb = 224;
     }
-    // fp32 state beyond the cache streams through HBM: two fused steps per
-    // launch move about half the bytes (512^3 D3Q19: 5.2-5.4 against 7.2 ms
-    // per two steps; 16384^2 D2Q9: 4.35 against 6.84 ms), when the second
-    // buffer fits on the device.  The 16-bit forms keep one step per launch:
-    // their collision already keeps the VALU busy enough that the fused pass
-    // is slower.
-    if (c->storage == LB_F32 && fused_eligible(c) && total > 320 * MB) {
-      const std::string keep = g_last_error;
-      if (ensure_state_b(c) == LB_OK) c->sched.fused = 1;
-      else g_last_error = keep;  // no room: one step per launch, not an error
-    }
+  }
+  // fp32 state beyond the cache streams through HBM: two fused steps per
+  // launch move about half the bytes (512^3 D3Q19: 5.2-5.4 against 7.2 ms
+  // per two steps; 16384^2 D2Q9: 4.35 against 6.84 ms), when the second
+  // buffer fits on the device; planes of 4 GiB or more included.  The
+  // 16-bit forms keep one step per launch: their collision already keeps the
+  // VALU busy enough that the fused pass is slower.
+  if (c->storage == LB_F32 && fused_eligible(c) && total > 320 * MB) {
+    const std::string keep = g_last_error;
+    if (ensure_state_b(c) == LB_OK) c->sched.fused = 1;
+    else g_last_error = keep;  // no room: one step per launch, not an error
   }
   return upload_schedule(c);
 }
@@ -1096,7 +1105,7 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s) {
   if (s->group_mb < 0 || s->group_mb > (1 << 20)) return fail(LB_EINVAL, "group_mb must be in [0, 2^20]");
   if (s->fused != 0 && s->fused != 1) return fail(LB_EINVAL, "fused must be 0 or 1");
   if (s->fused && !fused_eligible(ctx))
-    return fail(LB_EUNSUPPORTED, "the fused schedule needs a single lattice with planes below 4 GiB");
+    return fail(LB_EUNSUPPORTED, "the fused schedule needs a single lattice whose z-planes (D3Q19) or rows (D2Q9) stay below 4 GiB");
 
   HIP_TRY(hipSetDevice(ctx->device));
   if (s->fused) {

@@ -22,8 +22,10 @@
 //
 // The two steps compute exactly what two AA launches compute (same collision
 // code, same noise keys, 16-bit values rounded into the ring as they would be
-// stored), so the result is bit-identical to the AA pair.  PROP: the identity
-// collision (the data-movement floor of the pass).
+// stored), so the result is bit-identical to the AA pair.  Every access goes
+// through the descriptor of one row of one population plane, so planes of 4
+// GiB or more need no 64-bit offsets.  PROP: the identity collision (the
+// data-movement floor of the pass).
 #pragma once
 
 #include "lbf_kernels.h"
@@ -60,7 +62,7 @@ struct F2DRing {
   }
 };
 
-template <int S, bool PROP>
+template <int S, bool PROP, bool WIDE>
 __global__ void __launch_bounds__(F2D_THREADS)
 k_step2_2d(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* __restrict__ d_t, uint32_t t_off,
            uint32_t ntx, uint32_t nty, uint32_t ylen) {
@@ -112,9 +114,12 @@ k_step2_2d(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* _
     return yy < 0 ? ny - 1u : ((uint32_t)yy >= ny ? 0u : (uint32_t)yy);
   };
   auto load_row = [&](uint32_t it, U (&v)[Q]) {
-    const uint32_t so = yfirst(it) * nx * ES;
+    const uint32_t yf = yfirst(it);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) v[i] = Carry<T>::wrap(Raw<T>::template ld<0>(plane_rsrc(L, i, ES), x1 * ES, so));
+    for (int i = 0; i < Q; ++i) {
+      if constexpr (WIDE) v[i] = Carry<T>::wrap(Raw<T>::template ld<0>(slice_rsrc(L.base, L.plane, i, yf, nx, ES), x1 * ES, 0u));
+      else v[i] = Carry<T>::wrap(Raw<T>::template ld<0>(plane_rsrc(L, i, ES), x1 * ES, yf * nx * ES));
+    }
   };
   // first step of row u = it - 1: collide, push into P(u - 1), P(u), P(u + 1)
   auto first = [&](uint32_t it, const U (&v)[Q]) {
@@ -145,17 +150,31 @@ k_step2_2d(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* _
       const uint64_t t1 = t + 1u;
       collide<M>(L, d, x2 + y * nx, (uint32_t)t1, (uint32_t)(t1 >> 32));
     }
-    const uint32_t ry = y * nx;
-    const uint32_t rym = (y == 0 ? ny - 1u : y - 1u) * nx;
-    const uint32_t ryp = (y + 1u >= ny ? 0u : y + 1u) * nx;
+    if constexpr (WIDE) {  // one descriptor per row of each population plane
+      const uint32_t ym = y == 0 ? ny - 1u : y - 1u;
+      const uint32_t yp = y + 1u >= ny ? 0u : y + 1u;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const uint32_t ro = M::CY[j] > 0 ? ryp : (M::CY[j] < 0 ? rym : ry);
-      const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
-      const T v = PROP ? h[j] : C::enc(d[j]);
-      // x-shifted planes share lines with the neighbouring segments: cached; the others stream
-      if (M::CX[j] != 0) Raw<T>::template st<0>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
-      else Raw<T>::template st<CPOL_NT>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
+      for (int j = 0; j < Q; ++j) {
+        const uint32_t ys = M::CY[j] > 0 ? yp : (M::CY[j] < 0 ? ym : y);
+        const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
+        const T v = PROP ? h[j] : C::enc(d[j]);
+        const __amdgpu_buffer_rsrc_t r = slice_rsrc(dst_base, L.plane, j, ys, nx, ES);
+        // x-shifted planes share lines with the neighbouring segments: cached; the others stream
+        if (M::CX[j] != 0) Raw<T>::template st<0>(r, vx, v, 0u);
+        else Raw<T>::template st<CPOL_NT>(r, vx, v, 0u);
+      }
+    } else {  // one descriptor per population plane, the row in the uniform offset
+      const uint32_t ry = y * nx;
+      const uint32_t rym = (y == 0 ? ny - 1u : y - 1u) * nx;
+      const uint32_t ryp = (y + 1u >= ny ? 0u : y + 1u) * nx;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const uint32_t ro = M::CY[j] > 0 ? ryp : (M::CY[j] < 0 ? rym : ry);
+        const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
+        const T v = PROP ? h[j] : C::enc(d[j]);
+        if (M::CX[j] != 0) Raw<T>::template st<0>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
+        else Raw<T>::template st<CPOL_NT>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
+      }
     }
   };
 

@@ -726,7 +726,9 @@ k_propagate_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ 
 // The two steps compute exactly what two k_step launches compute (same
 // collision code, same noise keys, 16-bit values rounded into the ring as
 // they would be stored), so the result is bit-identical to the AA pair.
-// PROP: the identity collision (the data-movement floor of the pass).
+// Every access goes through the descriptor of one z-plane of one population
+// plane, so planes of 4 GiB or more need no 64-bit offsets.  PROP: the
+// identity collision (the data-movement floor of the pass).
 constexpr int F2_TY = 10;                     // interior rows per tile
 constexpr int F2_THREADS = (F2_TY + 3) * 64;  // interior + two halo-row + one halo-column waves
 
@@ -756,6 +758,8 @@ struct F2Ring {
   }
 };
 
+// Descriptor of population plane `plane` of the state at base (planes of
+// plane_elems elements, below 4 GiB).
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc_base(uint64_t base, uint64_t plane_elems, int plane,
                                                                   uint32_t esize) {
   const uint64_t bytes = plane_elems * esize;
@@ -763,7 +767,19 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc_base(uint64_t base,
                                            (int)(uint32_t)bytes, RAW_BUFFER_WORD3);
 }
 
-template <int S, bool PROP>
+// Descriptor of one slice of a population plane (a z-plane of a D3Q19 plane,
+// a row of a D2Q9 plane) of slice_elems elements: slice `slice` of plane
+// `plane` of the state at base.  Addressed slice by slice, a plane may
+// exceed the 32-bit range of one descriptor; only the slice must stay below
+// 4 GiB.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t slice_rsrc(uint64_t base, uint64_t plane_elems, int plane,
+                                                             uint32_t slice, uint32_t slice_elems, uint32_t esize) {
+  const uint64_t off = ((uint64_t)plane * plane_elems + (uint64_t)slice * slice_elems) * esize;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)(base + off), 0, (int)(slice_elems * esize),
+                                           RAW_BUFFER_WORD3);
+}
+
+template <int S, bool PROP, bool WIDE>
 __global__ void __launch_bounds__(F2_THREADS)
 k_step2(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* __restrict__ d_t, uint32_t t_off,
         uint32_t ntx, uint32_t nty, uint32_t zlen) {
@@ -824,9 +840,16 @@ k_step2(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* __re
     return zz < 0 ? nz - 1u : ((uint32_t)zz >= nz ? 0u : (uint32_t)zz);
   };
   auto load_plane = [&](uint32_t it, U (&v)[Q]) {
-    const uint32_t so = zfirst(it) * nxy * ES;
+    if constexpr (WIDE) {  // one descriptor per z-plane of each population plane
+      const uint32_t zf = zfirst(it);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) v[i] = Carry<T>::wrap(Raw<T>::template ld<0>(plane_rsrc(L, i, ES), sxy * ES, so));
+      for (int i = 0; i < Q; ++i)
+        v[i] = Carry<T>::wrap(Raw<T>::template ld<0>(slice_rsrc(L.base, L.plane, i, zf, nxy, ES), sxy * ES, 0u));
+    } else {  // one descriptor per population plane, the z-plane in the uniform offset
+      const uint32_t so = zfirst(it) * nxy * ES;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) v[i] = Carry<T>::wrap(Raw<T>::template ld<0>(plane_rsrc(L, i, ES), sxy * ES, so));
+    }
   };
   // first step of plane u = it - 1: collide, push into P(u - 1), P(u), P(u + 1)
   auto first = [&](uint32_t it, const U (&v)[Q]) {
@@ -858,18 +881,34 @@ k_step2(const LatDesc* __restrict__ src, uint64_t dst_base, const uint64_t* __re
       const uint64_t t1 = t + 1u;
       collide<M>(L, d, x2 + ry + z * nxy, (uint32_t)t1, (uint32_t)(t1 >> 32));
     }
-    const uint32_t rz = z * nxy;
-    const uint32_t rzm = (z == 0 ? nz - 1u : z - 1u) * nxy;
-    const uint32_t rzp = (z + 1u >= nz ? 0u : z + 1u) * nxy;
+    if constexpr (WIDE) {  // one descriptor per z-plane of each population plane
+      const uint32_t zm = z == 0 ? nz - 1u : z - 1u;
+      const uint32_t zp = z + 1u >= nz ? 0u : z + 1u;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const uint32_t ro = (M::CY[j] > 0 ? ryp : (M::CY[j] < 0 ? rym : ry)) +
-                          (M::CZ[j] > 0 ? rzp : (M::CZ[j] < 0 ? rzm : rz));
-      const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
-      const T v = PROP ? h[j] : C::enc(d[j]);
-      // x-shifted planes share lines with the neighbouring tiles: cached; the others stream
-      if (M::CX[j] != 0) Raw<T>::template st<0>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
-      else Raw<T>::template st<CPOL_NT>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
+      for (int j = 0; j < Q; ++j) {
+        const uint32_t zs = M::CZ[j] > 0 ? zp : (M::CZ[j] < 0 ? zm : z);
+        const uint32_t ro = M::CY[j] > 0 ? ryp : (M::CY[j] < 0 ? rym : ry);
+        const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
+        const T v = PROP ? h[j] : C::enc(d[j]);
+        const __amdgpu_buffer_rsrc_t r = slice_rsrc(dst_base, L.plane, j, zs, nxy, ES);
+        // x-shifted planes share lines with the neighbouring tiles: cached; the others stream
+        if (M::CX[j] != 0) Raw<T>::template st<0>(r, vx, v, ro * ES);
+        else Raw<T>::template st<CPOL_NT>(r, vx, v, ro * ES);
+      }
+    } else {  // one descriptor per population plane, the z-plane in the uniform offset
+      const uint32_t rz = z * nxy;
+      const uint32_t rzm = (z == 0 ? nz - 1u : z - 1u) * nxy;
+      const uint32_t rzp = (z + 1u >= nz ? 0u : z + 1u) * nxy;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const uint32_t ro = (M::CY[j] > 0 ? ryp : (M::CY[j] < 0 ? rym : ry)) +
+                            (M::CZ[j] > 0 ? rzp : (M::CZ[j] < 0 ? rzm : rz));
+        const uint32_t vx = M::CX[j] > 0 ? bxp : (M::CX[j] < 0 ? bxm : bx);
+        const T v = PROP ? h[j] : C::enc(d[j]);
+        // x-shifted planes share lines with the neighbouring tiles: cached; the others stream
+        if (M::CX[j] != 0) Raw<T>::template st<0>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
+        else Raw<T>::template st<CPOL_NT>(plane_rsrc_base(dst_base, L.plane, j, ES), vx, v, ro * ES);
+      }
     }
   };
 

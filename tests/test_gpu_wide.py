@@ -1,17 +1,23 @@
 """Planes of 4 GiB or more (here 1024^3 fp32: 2^30 sites, 19 planes of
-exactly 4 GiB, 81.6 GB of state) leave the buffer-descriptor path, whose
-range is a 32-bit byte count, and run the 64-bit-offset global-memory
-kernels.  Parity on sampled sites against the oracle's single-site update,
-both AA parities, with the default schedule (flat tiling; the row tiling is
-refused for such planes); propagation-only steps as exact shifts."""
+exactly 4 GiB, 81.6 GB of state) leave the plane-wide buffer-descriptor
+path, whose range is a 32-bit byte count: the AA steps run the 64-bit-offset
+global-memory kernels, and the fused two-step passes (the default schedule
+there) address each plane one z-plane at a time.  Parity on sampled sites
+against the oracle: AA steps of both parities against its single-site
+update (flat tiling; the row tiling is refused for such planes), a pair of
+fused passes against its evolution of each site's neighbourhood, and the
+fused schedule bit for bit against AA steps; propagation-only steps as
+exact shifts."""
 import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_0707_1581_amd as lbf
 from paper_0707_1581_amd import lb
-from tests.gpu_util import say
+from tests.gpu_util import oracle_params, say
 from tests.test_gpu_fullsize import check_one_step, sample_sites
+from tests.test_gpu_fused import _patch_oracle, _patch_oracle_2d
 
 pytestmark = pytest.mark.gpu
 
@@ -26,13 +32,14 @@ def test_1024_fp32_wide_planes_sampled_parity():
     say("1024^3 fp32 (4 GiB planes, 64-bit offsets)")
     lat = lbf.Lattice(**cfg, storage="f32", init="thermal")
     sched = lat.schedule()
-    assert sched["tiling"] == [0, 0]
+    assert sched["tiling"] == [0, 0] and sched["fused"] == 1, sched
     with pytest.raises(lb.LBError) as ei:
         lat.set_schedule(block=256, tiling=1)
     assert ei.value.code == lb.LB_EUNSUPPORTED
     with pytest.raises(lb.LBError) as ei:
         lat.set_schedule(block=256, tiling=0, resident=1)
     assert ei.value.code == lb.LB_EUNSUPPORTED
+    lat.set_schedule(block=256, xcd_remap=0, tiling=0, fused=0)  # AA steps only (the 64-bit-offset kernels)
     pts = sample_sites(L, 600, seed=9)
     check_one_step(lat, cfg, pts, 1e-5)      # even step
     lat.step(18)                             # one direct step, one 16-step graph replay, one more: t = 19
@@ -68,6 +75,131 @@ def test_1024_fp32_wide_planes_sampled_parity():
         torch.cuda.empty_cache()
         assert torch.equal(got, want[k]), k
     lat.close()
+
+
+def _fingerprint(state, L):
+    """Per-plane sums of the raw 32-bit patterns, and whole z-planes and
+    y-rows at the wrap and at tile and chunk seams, copied to the host."""
+    sums = [int(state[i].view(torch.int32).sum(dtype=torch.int64)) for i in range(state.shape[0])]
+    zs = torch.as_tensor([0, 1, 31, 32, 33, L - 1], device=state.device)
+    ys = torch.as_tensor([0, 9, 10, 11, L - 1], device=state.device)
+    return sums, state[:, zs].cpu(), state[:, :, ys].cpu()
+
+
+def test_1024_fp32_fused_wide_planes():
+    """The fused passes on 4 GiB planes (1024^3 fp32, where they are the
+    default schedule): one pair of passes from t = 0 at sampled sites (faces,
+    the last site and tile and chunk seams included) against the oracle's
+    evolution of each site's 9^3 neighbourhood, read straight from the even
+    AA state; then the state at t = 24 against AA steps from the same start,
+    bit for bit in per-plane checksums and in whole planes and rows at the
+    seams."""
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    if free < 180 * 2 ** 30:
+        pytest.skip("needs about 170 GB of free device memory")
+    L = 1024
+    cfg = dict(nx=L, ny=L, nz=L, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=-0.3,
+               gamma_even=0.2, seed=4243)
+    say("1024^3 fp32 fused passes (4 GiB planes, one z-plane per descriptor)")
+    lat = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    assert lat.schedule()["fused"] == 1, lat.schedule()
+    c, a, e, w = oracle.tables()
+    rng = np.random.default_rng(31)
+    pts = np.vstack([rng.integers(0, L, size=(16, 3)),
+                     [[0, 0, 0], [L - 1, L - 1, L - 1], [63, 9, 31], [64, 10, 32], [L - 1, 1019, 0], [0, L - 1, 33]]])
+    R = 4
+    off = np.arange(-R, R + 1)
+    patches = []
+    for x, y, z in pts:  # t = 0, even: plane i at site r holds d_i(r)
+        iz = torch.as_tensor((z + off) % L, device="cuda")[:, None, None]
+        iy = torch.as_tensor((y + off) % L, device="cuda")[None, :, None]
+        ix = torch.as_tensor((x + off) % L, device="cuda")[None, None, :]
+        d = lat.state[:, iz, iy, ix].double().cpu().numpy()
+        patches.append(a[:, None, None, None] * cfg["rho0"] * (1.0 + d))
+    lat.step(R)  # one pair of fused passes
+    idx = torch.as_tensor(pts, device="cuda")
+    got = lat.state[:, idx[:, 2], idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    got = a[:, None] * cfg["rho0"] * (1.0 + got)
+    p = oracle_params(cfg)
+    worst = 0.0
+    for k, center in enumerate(pts):
+        want = _patch_oracle(p, L, center, patches[k], 0, R)
+        worst = max(worst, float((np.abs(got[:, k] - want) / (a * cfg["rho0"])).max()))
+    say(f"  t=0 -> {R}: {len(pts)} sites, max scaled err {worst:.2e}")
+    assert worst < 1e-5, worst
+    lat.step(24 - lat.t)
+    assert lat.check()[0] == 0
+    fp = _fingerprint(lat.state, L)
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    ref = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    ref.set_schedule(block=256, xcd_remap=0, tiling=0, fused=0)
+    ref.step(24)
+    fr = _fingerprint(ref.state, L)
+    ref.close()
+    del ref
+    torch.cuda.empty_cache()
+    assert fp[0] == fr[0]
+    assert torch.equal(fp[1], fr[1]) and torch.equal(fp[2], fr[2])
+
+
+def test_32768_d2q9_fp32_fused_wide_planes():
+    """The D2Q9 fused passes on 4 GiB planes (32768^2 fp32, one row per
+    descriptor): one pair of passes from t = 0 at sampled sites against the
+    oracle's evolution of each site's 9^2 neighbourhood, read from the even
+    AA state; then the state at t = 24 bit for bit against AA steps."""
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    if free < 100 * 2 ** 30:
+        pytest.skip("needs about 80 GB of free device memory")
+    n = 32768
+    cfg = dict(nx=n, ny=n, nz=1, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=-0.3,
+               gamma_even=0.2, seed=4244, lattice="d2q9")
+    say("D2Q9 32768^2 fp32 fused passes (4 GiB planes, one row per descriptor)")
+    lat = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    assert lat.schedule()["fused"] == 1, lat.schedule()
+    a = oracle.tables(oracle.D2Q9)[1]
+    rng = np.random.default_rng(32)
+    pts = np.vstack([rng.integers(0, n, size=(20, 2)),
+                     [[0, 0], [n - 1, n - 1], [255, 31], [256, 32], [n - 1, 0], [0, n - 1]]])
+    R = 4
+    off = np.arange(-R, R + 1)
+    patches = []
+    for x, y in pts:
+        iy = torch.as_tensor((y + off) % n, device="cuda")[:, None]
+        ix = torch.as_tensor((x + off) % n, device="cuda")[None, :]
+        d = lat.state[:, 0, iy, ix].double().cpu().numpy()
+        patches.append(a[:, None, None] * cfg["rho0"] * (1.0 + d))
+    lat.step(R)
+    idx = torch.as_tensor(pts, device="cuda")
+    got = lat.state[:, 0, idx[:, 1], idx[:, 0]].double().cpu().numpy()
+    got = a[:, None] * cfg["rho0"] * (1.0 + got)
+    p = oracle_params(cfg)
+    worst = 0.0
+    for k, center in enumerate(pts):
+        want = _patch_oracle_2d(p, n, n, center, patches[k], 0, R)
+        worst = max(worst, float((np.abs(got[:, k] - want) / (a * cfg["rho0"])).max()))
+    say(f"  t=0 -> {R}: {len(pts)} sites, max scaled err {worst:.2e}")
+    assert worst < 1e-5, worst
+    lat.step(24 - lat.t)
+    assert lat.check()[0] == 0
+    sums = [int(lat.state[i].view(torch.int32).sum(dtype=torch.int64)) for i in range(9)]
+    rows = lat.state[:, 0, torch.as_tensor([0, 31, 32, 33, n - 1], device="cuda")].cpu()
+    cols = lat.state[:, 0, :, torch.as_tensor([0, 255, 256, n - 1], device="cuda")].cpu()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    ref = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    ref.set_schedule(block=256, xcd_remap=0, tiling=0, fused=0)
+    ref.step(24)
+    assert sums == [int(ref.state[i].view(torch.int32).sum(dtype=torch.int64)) for i in range(9)]
+    assert torch.equal(rows, ref.state[:, 0, torch.as_tensor([0, 31, 32, 33, n - 1], device="cuda")].cpu())
+    assert torch.equal(cols, ref.state[:, 0, :, torch.as_tensor([0, 255, 256, n - 1], device="cuda")].cpu())
+    ref.close()
+    del ref
+    torch.cuda.empty_cache()
 
 
 def test_largest_site_count_d2q9_f16():
