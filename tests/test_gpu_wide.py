@@ -77,6 +77,38 @@ def test_1024_fp32_wide_planes_sampled_parity():
     lat.close()
 
 
+def test_1024_fp32_wide_planes_noiseless():
+    """The kT = 0 branch of the 64-bit-offset D3Q19 AA kernels (the collision
+    branches at run time on whether the lattice is thermal): from a state
+    away from rest (two thermal steps of a noisy twin), one step of each
+    parity at sampled sites against the oracle's deterministic single-site
+    update."""
+    torch.cuda.empty_cache()
+    free, total = torch.cuda.mem_get_info()
+    if free < 200 * 2 ** 30:
+        pytest.skip("needs about 170 GB of free device memory")
+    L = 1024
+    cfg = dict(nx=L, ny=L, nz=L, rho0=1.0, kT=0.0, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=-0.3,
+               gamma_even=0.2, seed=4245)
+    say("1024^3 fp32 kT = 0 (64-bit-offset AA kernels)")
+    w = lbf.Lattice(**dict(cfg, kT=1e-4), storage="f32", init="thermal")
+    w.set_schedule(block=256, xcd_remap=0, tiling=0, fused=0)
+    w.step(2)
+    lat = lbf.Lattice(**cfg, storage="f32", init="rest")
+    lat.set_schedule(block=256, xcd_remap=0, tiling=0, fused=0)
+    lat.state.copy_(w.state)
+    w.close()
+    del w
+    torch.cuda.empty_cache()
+    pts = sample_sites(L, 300, seed=10)
+    check_one_step(lat, cfg, pts, 1e-5)      # even step
+    check_one_step(lat, cfg, pts, 1e-5)      # odd step
+    assert lat.check()[0] == 0
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+
+
 def _fingerprint(state, L):
     """Per-plane sums of the raw 32-bit patterns, and whole z-planes and
     y-rows at the wrap and at tile and chunk seams, copied to the host."""
