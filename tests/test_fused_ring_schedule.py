@@ -16,7 +16,10 @@ the destination, and checks that:
     is complete or overwritten before it is read;
   - within a phase the first step's slots and the second step's slots are
     disjoint, so one barrier per phase suffices;
-  - the halo-column wave's lanes cover the rows -1 .. TH of the tile.
+  - the halo-column wave's lanes cover the rows -1 .. TH of the tile;
+  - the slice descriptors of lattices with planes of 4 GiB or more (one
+    z-plane or row per descriptor) reach every site's byte address with a
+    lane offset inside the descriptor's 32-bit range.
 It needs no GPU; the GPU tests check the compiled kernels bit for bit
 against single steps and against the oracle."""
 import numpy as np
@@ -187,3 +190,45 @@ def test_ring_slot_lifetimes():
                     # held a plane outside the chunk (never read)
                     assert prev in (None, "read") or not (0 <= prev < ZC), (ZC, it, k, prev)
                     holder[(k, ws[k])] = target
+
+
+def _slice_access(base, plane_elems, plane, slice_idx, slice_elems, es, offset):
+    """Byte address and in-range flag of a buffer access through the fused
+    passes' slice descriptor (base + (plane * plane_elems + slice *
+    slice_elems) * es, range slice_elems * es, 32-bit lane offset)."""
+    desc = base + (plane * plane_elems + slice_idx * slice_elems) * es
+    rng = (slice_elems * es) & MASK32
+    return desc + offset, offset < rng
+
+
+MASK32 = 0xFFFFFFFF
+
+
+@pytest.mark.parametrize("dims,es", [((1024, 1024, 1024), 4), ((1625, 1625, 1625), 2), ((2048, 2048, 300), 4),
+                                     ((32768, 32768, 1), 4), ((65536, 65535, 1), 2), ((7, 5, 3), 4)])
+def test_slice_descriptors_address_every_site(dims, es):
+    """Planes of 4 GiB or more are addressed one z-plane (D3Q19) or one row
+    (D2Q9, nz = 1) per descriptor: for sampled sites of every population
+    plane (the last site included) the descriptor base, its range and the
+    lane offset give the site's byte address in the (q, nz, ny, nx) state,
+    with the offset inside the descriptor's range; the slice fits a 32-bit
+    range (the condition under which the library accepts the fused
+    schedule), while the whole plane may not."""
+    nx, ny, nz = dims
+    q = 9 if nz == 1 else 19
+    base = 1 << 40
+    plane = nx * ny * nz
+    if nz == 1:  # rows
+        slice_elems, nslices = nx, ny
+    else:        # z-planes
+        slice_elems, nslices = nx * ny, nz
+    assert slice_elems * es < 2 ** 32
+    rng = np.random.default_rng(nx + ny + nz)
+    sites = list(rng.integers(0, plane, size=200)) + [0, plane - 1, slice_elems - 1, slice_elems, plane - slice_elems]
+    for i in (0, 1, q - 1):
+        for s in sites:
+            s = int(s)
+            sl, within = divmod(s, slice_elems)
+            assert sl < nslices
+            addr, ok = _slice_access(base, plane, i, sl, slice_elems, es, within * es)
+            assert ok and addr == base + (i * plane + s) * es, (dims, i, s)
