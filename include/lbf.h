@@ -134,11 +134,11 @@ size_t lb_state_bytes(const lb_params* p);
  * Enqueues the initial state (init_kind) as the state at step count t0
  * (t0 >= 0); d_fields is required for LB_INIT_FIELDS and ignored otherwise.
  * The context stores p by value.  Its default schedule (lb_get_schedule)
- * depends on the state: an fp32 lattice (D3Q19 or D2Q9) of more than 320 MB
- * takes the fused two-step schedule when the device has room for its second
- * state buffer (and its z-planes, or D2Q9 rows, hold less than 4 GiB per
- * population), which lb_init then allocates (release
- * it with lb_set_schedule and fused = 0).  With LB_BF16 storage and kT = 0
+ * depends on the state: an fp32 lattice of more than 256 MiB (D3Q19) or
+ * 128 MiB (D2Q9) takes the fused two-step schedule when the device has room
+ * for its second state buffer (and its z-planes, or D2Q9 rows, hold less
+ * than 4 GiB per population), which lb_init then allocates (release it with
+ * lb_set_schedule and fused = 0).  With LB_BF16 storage and kT = 0
  * it succeeds and leaves a warning in lb_last_error(). */
 int lb_init(const lb_params* p, void* d_state, void* hip_stream, int32_t init_kind,
             const float* d_fields, int64_t t0, lb_ctx** out);

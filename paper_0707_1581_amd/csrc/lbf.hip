@@ -323,7 +323,7 @@ struct lb_ctx {
   LatDesc* d_f2 = nullptr;
   uint32_t f2_ntx = 0, f2_nty = 0, f2_ntz = 0, f2_len = 0;
   int f2_threads = 0;
-  static constexpr uint32_t F2_ZLEN = 32;   // planes per tile column (measured: 32 beats 64 and 128 at 512^3)
+  static constexpr uint32_t F2_ZLEN = 32;   // planes per tile column of large lattices (32 beats 64 and 128 at 512^3)
   static constexpr uint32_t F2D_YLEN = 32;  // rows per D2Q9 segment column (16384^2: 24-32 beat 16, 64 and 128)
   struct F2Args {
     const LatDesc* src;
@@ -343,6 +343,24 @@ void drop_graph(lb_ctx* c) {
   if (c->graph) (void)hipGraphDestroy(c->graph);
   c->graph_exec = nullptr;
   c->graph = nullptr;
+}
+
+// z-planes per tile column of the D3Q19 fused pass.  A CU holds a fixed
+// number of tiles at a time (one: their LDS ring), so a pass takes about
+// ceil(tiles / slots) rounds of one tile's zlen + 3 phases plus about one of
+// set-up.  Lattices with many rounds take 32 planes (the fastest at 512^3);
+// with few, a last round that leaves many CUs idle costs a large part of the
+// pass, and the chunk length from 8 to 32 that minimises the estimate is
+// taken instead (256^3 on 256 CUs: 22 planes, 5 rounds of 26 phases instead
+// of 4 of 36).  The result does not depend on it.
+uint32_t fused_zlen(uint32_t ntx, uint32_t nty, uint32_t nz, uint32_t slots) {
+  auto tiles = [&](uint32_t z) { return (uint64_t)ntx * nty * ((nz + z - 1u) / z); };
+  auto cost = [&](uint32_t z) { return ((tiles(z) + slots - 1u) / slots) * (uint64_t)(z + 4u); };
+  if (tiles(lb_ctx::F2_ZLEN) >= 16ull * slots) return lb_ctx::F2_ZLEN;
+  uint32_t best = lb_ctx::F2_ZLEN;
+  for (uint32_t z = 8; z < lb_ctx::F2_ZLEN; ++z)
+    if (cost(z) < cost(best)) best = z;
+  return best;
 }
 
 // Tile order, replica groups and the per-lattice block prefixes (relative to
@@ -404,10 +422,14 @@ int upload_schedule(lb_ctx* c) {
       c->f2_len = lb_ctx::F2D_YLEN;
       c->f2_threads = F2D_THREADS;
     } else {
+      int cus = 0, per_cu = 0;
+      HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step2_ptr(c->lattice, c->storage, c->wide, false),
+                                                           F2_THREADS, 0));
       c->f2_ntx = (f2[0].nx + 63u) / 64u;
       c->f2_nty = (f2[0].ny + (uint32_t)F2_TY - 1u) / (uint32_t)F2_TY;
-      c->f2_ntz = (f2[0].nz + lb_ctx::F2_ZLEN - 1u) / lb_ctx::F2_ZLEN;
-      c->f2_len = lb_ctx::F2_ZLEN;
+      c->f2_len = fused_zlen(c->f2_ntx, c->f2_nty, f2[0].nz, (uint32_t)std::max(1, cus * per_cu));
+      c->f2_ntz = (f2[0].nz + c->f2_len - 1u) / c->f2_len;
       c->f2_threads = F2_THREADS;
     }
   }
@@ -667,8 +689,10 @@ int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity
 // step row-tiled, with XCD groups of 8 consecutive tiles on D3Q19 and no
 // remapping on D2Q9 (groups of 8 made the D2Q9 bf16 step 10% slower).
 // State of 32 MB to 320 MB on one lattice runs resident in the Infinity
-// Cache (4-14% faster from 96^3 to 160^3); a batch whose replicas each fit
-// in 224 MiB runs resident groups of 224 MiB once it holds 32 MB or more
+// Cache (4-14% faster from 96^3 to 160^3), unless fp32 state above 256
+// MiB (D2Q9: 128 MiB) takes the fused pass (below); a batch whose replicas
+// each fit in 224 MiB runs resident groups of 224 MiB once it holds 32 MB or
+// more
 // (the 96-replica fp32 ensemble: 11% faster).  Below 32 MB the streaming
 // policy measured as fast or faster.  lb_autotune refines it for a given
 // workload.
@@ -695,10 +719,14 @@ int default_schedule(lb_ctx* c) {
   // fp32 state beyond the cache streams through HBM: two fused steps per
   // launch move about half the bytes (512^3 D3Q19: 5.2-5.4 against 7.2 ms
   // per two steps; 16384^2 D2Q9: 4.35 against 6.84 ms), when the second
-  // buffer fits on the device; planes of 4 GiB or more included.  The
+  // buffer fits on the device; planes of 4 GiB or more included.  Measured
+  // crossovers against the resident AA steps: D3Q19 between 152^3 (267 MB,
+  // AA 8% faster) and 156^3 (289 MB, fused 13% faster), D2Q9 between 1792^2
+  // (116 MB, AA 8% faster) and 2048^2 (151 MB, fused 20% faster).  The
   // 16-bit forms keep one step per launch: their collision already keeps the
   // VALU busy enough that the fused pass is slower.
-  if (c->storage == LB_F32 && fused_eligible(c) && total > 320 * MB) {
+  const uint64_t fused_above = c->lattice == LB_D2Q9 ? 128 * MIB : 256 * MIB;
+  if (c->storage == LB_F32 && fused_eligible(c) && total > fused_above) {
     const std::string keep = g_last_error;
     if (ensure_state_b(c) == LB_OK) c->sched.fused = 1;
     else g_last_error = keep;  // no room: one step per launch, not an error

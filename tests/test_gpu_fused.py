@@ -224,12 +224,14 @@ def test_fused_sampled_parity_full_size(box):
 def test_fused_schedule_rules():
     base = dict(rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=0.0, gamma_even=0.0, seed=9)
     # default: fp32 D3Q19 beyond the cache fused; cache-sized and 16-bit state one step per launch
-    for dims, st, want in [((192, 192, 192), "f32", 1), ((128, 128, 128), "f32", 0), ((256, 256, 256), "f16", 0)]:
+    for dims, st, want in [((192, 192, 192), "f32", 1), ((156, 156, 156), "f32", 1), ((152, 152, 152), "f32", 0),
+                           ((128, 128, 128), "f32", 0), ((256, 256, 256), "f16", 0)]:
         lat = lbf.Lattice(nx=dims[0], ny=dims[1], nz=dims[2], **base, storage=st, init="rest")
         assert lat.schedule()["fused"] == want, (dims, st, lat.schedule())
         lat.close()
     # D2Q9 likewise (4096^2 fp32: 604 MB; 2048^2: 151 MB, resident)
-    for dims, st, want in [((4096, 4096), "f32", 1), ((2048, 2048), "f32", 0), ((4096, 4096), "bf16", 0)]:
+    for dims, st, want in [((4096, 4096), "f32", 1), ((2048, 2048), "f32", 1), ((1792, 1792), "f32", 0),
+                           ((4096, 4096), "bf16", 0)]:
         lat = lbf.Lattice(nx=dims[0], ny=dims[1], nz=1, **base, storage=st, init="rest", lattice="d2q9")
         assert lat.schedule()["fused"] == want, (dims, st, lat.schedule())
         lat.close()
