@@ -135,7 +135,7 @@ size_t lb_state_bytes(const lb_params* p);
  * (t0 >= 0); d_fields is required for LB_INIT_FIELDS and ignored otherwise.
  * The context stores p by value.  Its default schedule (lb_get_schedule)
  * depends on the state: an fp32 lattice of more than 256 MiB (D3Q19) or
- * 128 MiB (D2Q9) takes the fused two-step schedule when the device has room
+ * 32 MiB (D2Q9) takes the fused two-step schedule when the device has room
  * for its second state buffer (and its z-planes, or D2Q9 rows, hold less
  * than 4 GiB per population), which lb_init then allocates (release it with
  * lb_set_schedule and fused = 0).  With LB_BF16 storage and kT = 0

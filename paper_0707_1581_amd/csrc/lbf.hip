@@ -323,8 +323,6 @@ struct lb_ctx {
   LatDesc* d_f2 = nullptr;
   uint32_t f2_ntx = 0, f2_nty = 0, f2_ntz = 0, f2_len = 0;
   int f2_threads = 0;
-  static constexpr uint32_t F2_ZLEN = 32;   // planes per tile column of large lattices (32 beats 64 and 128 at 512^3)
-  static constexpr uint32_t F2D_YLEN = 32;  // rows per D2Q9 segment column (16384^2: 24-32 beat 16, 64 and 128)
   struct F2Args {
     const LatDesc* src;
     uint64_t dst;
@@ -345,20 +343,22 @@ void drop_graph(lb_ctx* c) {
   c->graph = nullptr;
 }
 
-// z-planes per tile column of the D3Q19 fused pass.  A CU holds a fixed
-// number of tiles at a time (one: their LDS ring), so a pass takes about
-// ceil(tiles / slots) rounds of one tile's zlen + 3 phases plus about one of
-// set-up.  Lattices with many rounds take 32 planes (the fastest at 512^3);
-// with few, a last round that leaves many CUs idle costs a large part of the
-// pass, and the chunk length from 8 to 32 that minimises the estimate is
-// taken instead (256^3 on 256 CUs: 22 planes, 5 rounds of 26 phases instead
-// of 4 of 36).  The result does not depend on it.
-uint32_t fused_zlen(uint32_t ntx, uint32_t nty, uint32_t nz, uint32_t slots) {
-  auto tiles = [&](uint32_t z) { return (uint64_t)ntx * nty * ((nz + z - 1u) / z); };
+// Planes (D3Q19: z-planes; D2Q9: rows) per tile column of the fused pass,
+// for `across` tiles per plane, `extent` planes and `slots` tiles resident
+// on the device at a time (CUs times tiles per CU).  A pass runs in rounds
+// of `slots` tiles, each round taking one tile's chunk + 3 phases plus about
+// one of set-up.  Lattices with many rounds take 32 planes (the fastest at
+// 512^3 and 16384^2); with few, a last round that leaves many CUs idle costs
+// a large part of the pass, and the chunk length from 8 to 32 that
+// minimises the estimate is taken instead (256^3 on 256 CUs: 22 planes, 5
+// rounds of 26 phases instead of 4 of 36).  The result does not depend on it.
+uint32_t fused_chunk(uint64_t across, uint32_t extent, uint32_t slots) {
+  constexpr uint32_t LONG = 32;
+  auto tiles = [&](uint32_t z) { return across * ((extent + z - 1u) / z); };
   auto cost = [&](uint32_t z) { return ((tiles(z) + slots - 1u) / slots) * (uint64_t)(z + 4u); };
-  if (tiles(lb_ctx::F2_ZLEN) >= 16ull * slots) return lb_ctx::F2_ZLEN;
-  uint32_t best = lb_ctx::F2_ZLEN;
-  for (uint32_t z = 8; z < lb_ctx::F2_ZLEN; ++z)
+  if (tiles(LONG) >= 16ull * slots) return LONG;
+  uint32_t best = LONG;
+  for (uint32_t z = 8; z < LONG; ++z)
     if (cost(z) < cost(best)) best = z;
   return best;
 }
@@ -415,22 +415,23 @@ int upload_schedule(lb_ctx* c) {
     LatDesc f2[2] = {c->lats[0], c->lats[0]};
     f2[1].base = (uint64_t)(uintptr_t)c->d_state_b;
     HIP_TRY(hipMemcpy(c->d_f2, f2, sizeof(f2), hipMemcpyHostToDevice));
-    if (c->lattice == LB_D2Q9) {
+    const bool d2 = c->lattice == LB_D2Q9;
+    c->f2_threads = d2 ? F2D_THREADS : F2_THREADS;
+    int cus = 0, per_cu = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step2_ptr(c->lattice, c->storage, c->wide, false),
+                                                         c->f2_threads, 0));
+    const uint32_t slots = (uint32_t)std::max(1, cus * per_cu);
+    if (d2) {
       c->f2_ntx = (f2[0].nx + (uint32_t)F2D_W - 1u) / (uint32_t)F2D_W;
-      c->f2_nty = (f2[0].ny + lb_ctx::F2D_YLEN - 1u) / lb_ctx::F2D_YLEN;
+      c->f2_len = fused_chunk(c->f2_ntx, f2[0].ny, slots);
+      c->f2_nty = (f2[0].ny + c->f2_len - 1u) / c->f2_len;
       c->f2_ntz = 1;
-      c->f2_len = lb_ctx::F2D_YLEN;
-      c->f2_threads = F2D_THREADS;
     } else {
-      int cus = 0, per_cu = 0;
-      HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, step2_ptr(c->lattice, c->storage, c->wide, false),
-                                                           F2_THREADS, 0));
       c->f2_ntx = (f2[0].nx + 63u) / 64u;
       c->f2_nty = (f2[0].ny + (uint32_t)F2_TY - 1u) / (uint32_t)F2_TY;
-      c->f2_len = fused_zlen(c->f2_ntx, c->f2_nty, f2[0].nz, (uint32_t)std::max(1, cus * per_cu));
+      c->f2_len = fused_chunk((uint64_t)c->f2_ntx * c->f2_nty, f2[0].nz, slots);
       c->f2_ntz = (f2[0].nz + c->f2_len - 1u) / c->f2_len;
-      c->f2_threads = F2_THREADS;
     }
   }
   drop_graph(c);
@@ -690,7 +691,7 @@ int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity
 // remapping on D2Q9 (groups of 8 made the D2Q9 bf16 step 10% slower).
 // State of 32 MB to 320 MB on one lattice runs resident in the Infinity
 // Cache (4-14% faster from 96^3 to 160^3), unless fp32 state above 256
-// MiB (D2Q9: 128 MiB) takes the fused pass (below); a batch whose replicas
+// MiB (D2Q9: 32 MiB) takes the fused pass (below); a batch whose replicas
 // each fit in 224 MiB runs resident groups of 224 MiB once it holds 32 MB or
 // more
 // (the 96-replica fp32 ensemble: 11% faster).  Below 32 MB the streaming
@@ -721,11 +722,11 @@ int default_schedule(lb_ctx* c) {
   // per two steps; 16384^2 D2Q9: 4.35 against 6.84 ms), when the second
   // buffer fits on the device; planes of 4 GiB or more included.  Measured
   // crossovers against the resident AA steps: D3Q19 between 152^3 (267 MB,
-  // AA 8% faster) and 156^3 (289 MB, fused 13% faster), D2Q9 between 1792^2
-  // (116 MB, AA 8% faster) and 2048^2 (151 MB, fused 20% faster).  The
-  // 16-bit forms keep one step per launch: their collision already keeps the
-  // VALU busy enough that the fused pass is slower.
-  const uint64_t fused_above = c->lattice == LB_D2Q9 ? 128 * MIB : 256 * MIB;
+  // AA 8% faster) and 156^3 (289 MB, fused 13% faster), D2Q9 between 724^2
+  // (19 MB, AA 6% faster) and 1024^2 (38 MB, fused 11% faster).  The 16-bit
+  // forms keep one step per launch: their collision already keeps the VALU
+  // busy enough that the fused pass is slower.
+  const uint64_t fused_above = c->lattice == LB_D2Q9 ? 32 * MIB : 256 * MIB;
   if (c->storage == LB_F32 && fused_eligible(c) && total > fused_above) {
     const std::string keep = g_last_error;
     if (ensure_state_b(c) == LB_OK) c->sched.fused = 1;

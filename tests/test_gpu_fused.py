@@ -230,7 +230,7 @@ def test_fused_schedule_rules():
         assert lat.schedule()["fused"] == want, (dims, st, lat.schedule())
         lat.close()
     # D2Q9 likewise (4096^2 fp32: 604 MB; 2048^2: 151 MB, resident)
-    for dims, st, want in [((4096, 4096), "f32", 1), ((2048, 2048), "f32", 1), ((1792, 1792), "f32", 0),
+    for dims, st, want in [((4096, 4096), "f32", 1), ((1024, 1024), "f32", 1), ((724, 724), "f32", 0),
                            ((4096, 4096), "bf16", 0)]:
         lat = lbf.Lattice(nx=dims[0], ny=dims[1], nz=1, **base, storage=st, init="rest", lattice="d2q9")
         assert lat.schedule()["fused"] == want, (dims, st, lat.schedule())
