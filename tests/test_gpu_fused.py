@@ -221,6 +221,30 @@ def test_fused_sampled_parity_full_size(box):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("lattice,dims", [("d3q19", (176, 176, 176)), ("d3q19", (256, 256, 256)),
+                                          ("d3q19", (130, 1000, 40)), ("d2q9", (2048, 2048, 1)), ("d2q9", (1000, 3000, 1))])
+def test_fused_tail_aware_chunks(lattice, dims):
+    """Lattices with few rounds of tiles, where the host shortens the chunks
+    a tile walks (z-planes or rows; 176^3: 20, 256^3: 22, 2048^2: 13): the
+    fused schedule equals AA steps bit for bit."""
+    nx, ny, nz = dims
+    cfg = dict(nx=nx, ny=ny, nz=nz, rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=-0.3,
+               gamma_even=0.2, seed=77, lattice=lattice)
+    a = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    assert a.schedule()["fused"] == 1, a.schedule()
+    b = lbf.Lattice(**cfg, storage="f32", init="thermal")
+    b.set_schedule(**dict(b.schedule(), fused=0))
+    for n in (5, 16):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.state, b.state), (dims, a.t)
+    assert a.check()[0] == 0
+    a.close()
+    b.close()
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def test_fused_schedule_rules():
     base = dict(rho0=1.0, kT=1e-4, gamma_bulk=0.5, gamma_shear=0.8, gamma_odd=0.0, gamma_even=0.0, seed=9)
     # default: fp32 D3Q19 beyond the cache fused; cache-sized and 16-bit state one step per launch
