@@ -301,7 +301,13 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s);
  * resident, group_mb, fused and ms_per_step) into report (NUL-terminated,
  * truncated to report_len).  Allocates a scratch copy of the state for as
  * long as it runs; returns LB_EUNSUPPORTED, having changed nothing, when the
- * device's free memory cannot hold that copy. */
+ * device's free memory cannot hold that copy.
+ * Cache: when the environment variable LBF_TUNE_CACHE names a file, a
+ * schedule tuned earlier for the same device, library build, lattice,
+ * storage and replica boxes (and noise on or off) is read from it and
+ * applied without timing (report: [{"cached":true,"key":...}]); otherwise
+ * the tuned schedule is appended to it.  An unreadable or unwritable file
+ * only disables the cache; concurrent writers append whole lines. */
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
 
 /* ---- a step entry point that allocates nothing ---- */

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -1147,10 +1148,103 @@ int lb_set_schedule(lb_ctx* ctx, const lb_schedule* s) {
   return rc;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Autotune cache (LBF_TUNE_CACHE): one line per tuned workload, its key and
+// the schedule fields, appended after each timed tuning; the last line with
+// a matching key wins.  The key names the device (architecture and CU
+// count), this build of the library, the lattice and storage, and every
+// replica's box and noise flag in tile order, so a schedule is reused only
+// for the workload and kernels it was timed on.
+std::string tune_key(const lb_ctx* c) {
+  hipDeviceProp_t prop;
+  std::string dev = "unknown";
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess)
+    dev = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the replica boxes and noise flags
+  auto mix = [&](uint64_t v) {
+    for (int b = 0; b < 8; ++b) {
+      h ^= (v >> (8 * b)) & 0xFF;
+      h *= 1099511628211ull;
+    }
+  };
+  for (const lb_params& p : c->reps) {
+    mix(((uint64_t)p.nx << 32) | (uint32_t)p.ny);
+    mix(((uint64_t)p.nz << 1) | (p.kT > 0.0 ? 1u : 0u));
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "%s|%s %s|lattice%d|storage%d|n%zu|%dx%dx%d|%016llx", dev.c_str(), __DATE__,
+                __TIME__, c->lattice, c->storage, c->reps.size(), c->reps[0].nx, c->reps[0].ny, c->reps[0].nz,
+                (unsigned long long)h);
+  return buf;
+}
+
+bool tune_cache_find(const char* path, const std::string& key, lb_schedule* out) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  bool found = false;
+  char line[1024];
+  while (std::fgets(line, sizeof(line), f)) {
+    const char* tab = std::strchr(line, '\t');
+    if (!tab || (size_t)(tab - line) != key.size() || std::strncmp(line, key.data(), key.size()) != 0) continue;
+    lb_schedule s{};
+    if (std::sscanf(tab + 1, "%d %d %d %d %d %d %d %d %d %d", &s.block, &s.order, &s.graph_chunk, &s.xcd_remap[0],
+                    &s.xcd_remap[1], &s.tiling[0], &s.tiling[1], &s.resident, &s.group_mb, &s.fused) == 10) {
+      *out = s;
+      found = true;
+    }
+  }
+  std::fclose(f);
+  return found;
+}
+
+void tune_cache_add(const char* path, const std::string& key, const lb_schedule& s) {
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;  // the tuned schedule is applied either way
+  std::fprintf(f, "%s\t%d %d %d %d %d %d %d %d %d %d\n", key.c_str(), s.block, s.order, s.graph_chunk, s.xcd_remap[0],
+               s.xcd_remap[1], s.tiling[0], s.tiling[1], s.resident, s.group_mb, s.fused);
+  std::fclose(f);
+}
+
+int autotune_timed(lb_ctx* ctx, int32_t steps, char* report, size_t report_len);
+
+}  // namespace
+
+extern "C" {
+
 int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   if (!ctx) return fail(LB_EINVAL, "ctx is NULL");
   if (ctx->parent) return fail(LB_EINVAL, "tune the batch, not a view");
   if (steps < 2) return fail(LB_EINVAL, "steps must be >= 2");
+  HIP_TRY(hipSetDevice(ctx->device));
+  const char* path = std::getenv("LBF_TUNE_CACHE");
+  const bool cache = path && *path;
+  const std::string key = cache ? tune_key(ctx) : std::string();
+  lb_schedule s{};
+  if (cache && tune_cache_find(path, key, &s)) {
+    const std::string keep = g_last_error;
+    if (lb_set_schedule(ctx, &s) == LB_OK) {
+      if (report && report_len) {
+        const std::string rep = "[{\"cached\":true,\"key\":\"" + key + "\"}]";
+        std::strncpy(report, rep.c_str(), report_len - 1);
+        report[report_len - 1] = 0;
+      }
+      return LB_OK;
+    }
+    g_last_error = keep;  // e.g. no room for the fused pass's buffer now: tune afresh
+  }
+  const int rc = autotune_timed(ctx, steps, report, report_len);
+  if (rc == LB_OK && cache) tune_cache_add(path, key, ctx->sched);
+  return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+int autotune_timed(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   HIP_TRY(hipSetDevice(ctx->device));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
 
@@ -1376,6 +1470,10 @@ int lb_autotune(lb_ctx* ctx, int32_t steps, char* report, size_t report_len) {
   }
   return rc ? rc : rc2;
 }
+
+}  // namespace
+
+extern "C" {
 
 int lb_step_noalloc(const lb_params* reps, int32_t nrep, void* d_pool, void* hip_stream, int64_t t0,
                     int64_t nsteps) {
