@@ -163,6 +163,16 @@ def test_1024_fp32_fused_wide_planes():
     lat.step(24 - lat.t)
     assert lat.check()[0] == 0
     fp = _fingerprint(lat.state, L)
+    # propagation only under the fused schedule (one pair of identity-collision
+    # passes from even t): every population moves by 4 c_i, read from the raw
+    # even-layout state at sampled sites
+    spts = torch.as_tensor(np.vstack([pts, rng.integers(0, L, size=(400, 3))]), device="cuda")
+    before = {i: lat.state[i].clone() for i in (0, 1, 6, 7, 18)}
+    lat.propagate(4)
+    for i, plane in before.items():
+        src = [(spts[:, k] - 4 * int(c[i, k])) % L for k in range(3)]
+        assert torch.equal(lat.state[i, spts[:, 2], spts[:, 1], spts[:, 0]], plane[src[2], src[1], src[0]]), i
+    del before
     lat.close()
     del lat
     torch.cuda.empty_cache()
