@@ -451,7 +451,6 @@ bool fused_eligible(const lb_ctx* c) {
 
 // The fused schedule's second buffer: allocated once, the size of the state,
 // if the device has room for it beside a margin of 1 GiB.
-
 int ensure_state_b(lb_ctx* c) {
   if (c->d_state_b) return LB_OK;
   const size_t bytes = (size_t)q_of(c->lattice) * sites_of(c->reps[0]) * elem_size(c->storage);
@@ -691,10 +690,9 @@ int init_lattice(lb_ctx* c, int idx, int kind, const float* d_fields, int parity
 // step row-tiled, with XCD groups of 8 consecutive tiles on D3Q19 and no
 // remapping on D2Q9 (groups of 8 made the D2Q9 bf16 step 10% slower).
 // State of 32 MB to 320 MB on one lattice runs resident in the Infinity
-// Cache (4-14% faster from 96^3 to 160^3), unless fp32 state above 256
-// MiB (D2Q9: 32 MiB) takes the fused pass (below); a batch whose replicas
-// each fit in 224 MiB runs resident groups of 224 MiB once it holds 32 MB or
-// more
+// Cache (4-14% faster from 96^3 to 160^3), unless fp32 state above 256 MiB
+// (D2Q9: 32 MiB) takes the fused pass (below); a batch whose replicas each
+// fit in 224 MiB runs resident groups of 224 MiB once it holds 32 MB or more
 // (the 96-replica fp32 ensemble: 11% faster).  Below 32 MB the streaming
 // policy measured as fast or faster.  lb_autotune refines it for a given
 // workload.
@@ -1156,8 +1154,8 @@ namespace {
 // the schedule fields, appended after each timed tuning; the last line with
 // a matching key wins.  The key names the device (architecture and CU
 // count), this build of the library, the lattice and storage, and every
-// replica's box and noise flag in tile order, so a schedule is reused only
-// for the workload and kernels it was timed on.
+// replica's box and noise flag in the order given, so a schedule is reused
+// only for the workload and kernels it was timed on.
 std::string tune_key(const lb_ctx* c) {
   hipDeviceProp_t prop;
   std::string dev = "unknown";
