@@ -22,10 +22,11 @@
 //
 // The two steps compute exactly what two AA launches compute (same collision
 // code, same noise keys, 16-bit values rounded into the ring as they would be
-// stored), so the result is bit-identical to the AA pair.  Every access goes
-// through the descriptor of one row of one population plane, so planes of 4
-// GiB or more need no 64-bit offsets.  PROP: the identity collision (the
-// data-movement floor of the pass).
+// stored), so the result is bit-identical to the AA pair.  WIDE (planes of 4
+// GiB or more): every access goes through the descriptor of one row of one
+// population plane, so no 64-bit offsets are needed; smaller planes take one
+// descriptor per plane.  PROP: the identity collision (the data-movement
+// floor of the pass).
 #pragma once
 
 #include "lbf_kernels.h"

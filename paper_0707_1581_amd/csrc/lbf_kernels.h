@@ -726,9 +726,10 @@ k_propagate_rows(const LatDesc* __restrict__ lats, const uint32_t* __restrict__ 
 // The two steps compute exactly what two k_step launches compute (same
 // collision code, same noise keys, 16-bit values rounded into the ring as
 // they would be stored), so the result is bit-identical to the AA pair.
-// Every access goes through the descriptor of one z-plane of one population
-// plane, so planes of 4 GiB or more need no 64-bit offsets.  PROP: the
-// identity collision (the data-movement floor of the pass).
+// WIDE (planes of 4 GiB or more): every access goes through the descriptor
+// of one z-plane of one population plane, so no 64-bit offsets are needed;
+// smaller planes take one descriptor per plane.  PROP: the identity
+// collision (the data-movement floor of the pass).
 constexpr int F2_TY = 10;                     // interior rows per tile
 constexpr int F2_THREADS = (F2_TY + 3) * 64;  // interior + two halo-row + one halo-column waves
 
