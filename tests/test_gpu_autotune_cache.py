@@ -47,3 +47,25 @@ def test_autotune_cache_unwritable(tmp_path, monkeypatch):
     a.step(4)
     assert a.check()[0] == 0
     a.close()
+
+
+def test_autotune_cache_ignores_malformed_lines(tmp_path, monkeypatch):
+    """Lines that are not `key<TAB>ten integers` are skipped: a matching key
+    with a malformed schedule is tuned afresh, and the tuned line appended
+    after it is used from then on."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("LBF_TUNE_CACHE", str(path))
+    a = lbf.Lattice(40, 36, 32, **BASE, seed=1, init="thermal")
+    a.autotune(steps=4)
+    key = path.read_text().split("\t")[0]
+    path.write_text("garbage without a tab\n" + key + "\t256 0 16\n" + "\t\n")
+    b = lbf.Lattice(40, 36, 32, **BASE, seed=2, init="thermal")
+    rb = json.loads(b.autotune(steps=4))
+    assert not any(r.get("cached") for r in rb)
+    lines = path.read_text().splitlines()
+    assert len(lines) == 4 and lines[-1].startswith(key + "\t")
+    c = lbf.Lattice(40, 36, 32, **BASE, seed=3, init="thermal")
+    assert json.loads(c.autotune(steps=4))[0]["cached"] is True
+    assert c.schedule() == b.schedule()
+    for lat in (a, b, c):
+        lat.close()
